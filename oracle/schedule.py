@@ -1,0 +1,71 @@
+"""Step schedule of block-pair updates (the reading adopted for the paper's
+TEBD step on the snake-ordered block MPS).
+
+The paper applies the gates of one Trotter step (eq. "trotter_step") to a
+snake-ordered MPS of half-row blocks (results section; supplement section
+"MPS Ordering"). Every ZZ coupling between two blocks is applied as one
+diagonal d_a x d_b phase gate on the two sites, and blocks that are not
+neighbours in the chain are brought together by SWAP updates. One step:
+
+  A  vertical pairs between rows r and r+1 that face each other in the chain;
+  B  the horizontal pair of every row, fused with a SWAP (each row reverses);
+  C  the vertical pairs that face each other after B;
+  W  (periodic, R >= 3) the wrap pairs between row R-1 and row 0: the row
+     R-1 block is swapped leftwards until it neighbours its row-0 partner,
+     the gate is applied, and it is swapped back;
+  X  the single-site layer exp(-i h dt X) (times the intra-block ZZ phases).
+
+Ops are tuples:
+  ("U2", site, swap, gate, block_at_site, block_at_site_plus_1)
+  ("U1", site, variant, block)   variant 0: U_X(h dt) * D_intra   (order 1)
+                                 variant 1: D_intra * U_X(h dt/2) (order 2, first)
+                                 variant 2: U_X(h dt/2)           (order 2, last)
+"""
+from __future__ import annotations
+
+from .lattice import Grid, pair_coupled
+
+
+def step_ops(grid: Grid, pos: list[int], order: int = 1) -> list[tuple]:
+    """Ops of one Trotter step starting from chain order ``pos``; ``pos`` is
+    updated in place to the order at the end of the step."""
+    R = grid.rows
+    ops: list[tuple] = []
+
+    def u2(site: int, swap: bool, gate: bool):
+        a, b = pos[site], pos[site + 1]
+        if gate and not pair_coupled(grid, a, b):
+            gate = False
+        ops.append(("U2", site, int(swap), int(gate), a, b))
+        if swap:
+            pos[site], pos[site + 1] = pos[site + 1], pos[site]
+
+    if order == 2:
+        for p in range(len(pos)):
+            ops.append(("U1", p, 1, pos[p]))
+    for r in range(R - 1):                      # A
+        u2(2 * r + 1, False, True)
+    for r in range(R):                          # B
+        u2(2 * r, True, True)
+    for r in range(R - 1):                      # C
+        u2(2 * r + 1, False, True)
+    if grid.periodic and R >= 3:                # W
+        for p0 in (1, 0):
+            target = 2 * (R - 1) + (pos[p0] % 2)
+            t = pos.index(target)
+            for p in range(t - 1, p0, -1):
+                u2(p, True, False)
+            u2(p0, False, True)
+            for p in range(p0 + 1, t):
+                u2(p, True, False)
+    for p in range(len(pos)):                   # X
+        ops.append(("U1", p, 0 if order == 1 else 2, pos[p]))
+    return ops
+
+
+def schedule(grid: Grid, nsteps: int, order: int = 1) -> list[tuple]:
+    pos = grid.snake()
+    out = []
+    for _ in range(nsteps):
+        out += step_ops(grid, pos, order)
+    return out

@@ -1,0 +1,285 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these checks re-runs the oracle's own formula: each compares it with
+an independent construction (dense Hamiltonian and matrix exponentials), a
+closed form (single-qubit precession at J = 0, conservation at h = 0, the
+product state at s = 0), exact state-vector evolution (full bond dimension),
+or a property the paper states (the kept/discarded decomposition of a
+truncation, unit norm, monotone fidelity).
+"""
+import copy
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import estimators, mps, statevector
+from oracle.lattice import Grid, pair_coupled
+from oracle.schedule import step_ops
+
+J, H, DT = -1.0, 2.0, 0.25
+
+
+# --------------------------------------------------------------------------
+# independent dense construction of H_ZZ and H_X (Kronecker products)
+def _dense_h(R, C):
+    n = R * C
+    I2 = np.eye(2)
+    Zm = np.diag([1.0, -1.0])
+    Xm = np.array([[0.0, 1.0], [1.0, 0.0]])
+
+    def op(single, q):
+        out = np.ones((1, 1))
+        for k in range(n):
+            out = np.kron(out, single if k == q else I2)
+        return out
+
+    pairs = set()
+    for r in range(R):
+        for c in range(C):
+            for (r2, c2) in (((r + 1) % R, c), (r, (c + 1) % C)):
+                a, b = r * C + c, r2 * C + c2
+                if a != b:
+                    pairs.add((min(a, b), max(a, b)))
+    hzz = sum(op(Zm, a) @ op(Zm, b) for (a, b) in pairs)
+    hx = sum(op(Xm, q) for q in range(n))
+    return hzz, hx, len(pairs)
+
+
+@pytest.mark.parametrize("R,C", [(2, 2), (2, 3), (3, 3), (1, 4)])
+@pytest.mark.parametrize("order", [1, 2])
+def test_statevector_matches_dense_expm(R, C, order):
+    hzz, hx, npairs = _dense_h(R, C)
+    g = Grid(R, C)
+    assert len(g.zz_bonds()) == npairs
+    th = 0.37
+    if order == 1:
+        U = scipy.linalg.expm(-1j * DT * H * hx) @ scipy.linalg.expm(-1j * DT * J * hzz)
+    else:
+        half = scipy.linalg.expm(-0.5j * DT * H * hx)
+        U = half @ scipy.linalg.expm(-1j * DT * J * hzz) @ half
+    psi = np.ones(1)
+    for _ in range(R * C):
+        psi = np.kron(psi, [math.cos(th / 2), math.sin(th / 2)])
+    sv = statevector.StateVector(g, th, J, H, DT, order)
+    for _ in range(3):
+        psi = U @ psi
+        sv.step()
+    assert np.max(np.abs(sv.psi - psi)) < 1e-12
+
+
+def test_bond_counts_periodic():
+    # 2n nearest-neighbour bonds on a periodic grid with R, C >= 3
+    for (R, C) in [(4, 4), (5, 6), (6, 8), (7, 8), (3, 3)]:
+        assert len(Grid(R, C).zz_bonds()) == 2 * R * C
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("R,C", [(3, 3), (4, 4), (2, 5)])
+@pytest.mark.parametrize("th", [0.0, 0.3, math.pi / 18, 2.0])
+def test_t1_initial_state(R, C, th):
+    g = Grid(R, C)
+    n = g.n
+    m = mps.BlockMPS(g, 8, th, J, H, DT).measure()
+    s = statevector.StateVector(g, th, J, H, DT).measure()
+    for o in (m, s):
+        assert abs(o["z"] - math.cos(th)) < 1e-14
+        assert abs(o["z2"] - (1 / n + (1 - 1 / n) * math.cos(th) ** 2)) < 1e-14
+    assert m["fidelity"] == 1.0
+
+
+@pytest.mark.parametrize("R,C,chi", [(3, 3, 4), (4, 4, 2), (3, 4, 16)])
+def test_t2_no_coupling_precession(R, C, chi):
+    g = Grid(R, C)
+    n = g.n
+    th = 0.41
+    m = mps.BlockMPS(g, chi, th, 0.0, H, DT)
+    sv = statevector.StateVector(g, th, 0.0, H, DT)
+    for s in range(1, 6):
+        m.step()
+        sv.step()
+        zc = math.cos(th) * math.cos(2 * H * DT * s)
+        z2c = 1 / n + (1 - 1 / n) * (math.cos(th) * math.cos(2 * H * DT * s)) ** 2
+        for o in (m.measure(), sv.measure()):
+            assert abs(o["z"] - zc) < 1e-12
+            assert abs(o["z2"] - z2c) < 1e-12
+        assert abs(m.log_fidelity) < 1e-12
+    for b in range(1, len(m.sites)):
+        sv_b = m.bond_spectrum(b)
+        assert np.sum(sv_b > 1e-10) == 1      # product state: Schmidt rank 1
+
+
+@pytest.mark.parametrize("th", [0.0, 0.7])
+def test_t3_no_field_conserves(th):
+    g = Grid(3, 4)
+    m = mps.BlockMPS(g, 64, th, J, 0.0, DT)
+    z0 = m.measure()
+    for _ in range(3):
+        m.step()
+        o = m.measure()
+        assert abs(o["z"] - z0["z"]) < 1e-10
+        assert abs(o["z2"] - z0["z2"]) < 1e-10
+    if th == 0.0:
+        assert abs(o["z"] - 1) < 1e-12 and abs(o["z2"] - 1) < 1e-12
+        assert abs(o["fidelity"] - 1) < 1e-12
+
+
+def _perm_statevector(g, pos, psi):
+    """Reshape a dense state into chain order (blocks of pos, in-block MSB first)."""
+    n = g.n
+    order = [q for b in pos for q in g.block_qubits(b)]
+    t = psi.reshape([2] * n).transpose(order)
+    return t.reshape(-1)
+
+
+@pytest.mark.parametrize("R,C,chi,steps,order", [
+    (3, 3, 64, 4, 1), (2, 4, 16, 4, 1), (4, 4, 256, 3, 1), (3, 4, 64, 3, 2),
+    (2, 3, 8, 5, 2)])
+def test_t4_full_bond_dimension_is_exact(R, C, chi, steps, order):
+    g = Grid(R, C)
+    th = 0.6
+    m = mps.BlockMPS(g, chi, th, J, H, DT, order)
+    sv = statevector.StateVector(g, th, J, H, DT, order)
+    for _ in range(steps):
+        m.step()
+        sv.step()
+        a, b = m.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < 1e-10
+        assert abs(a["z2"] - b["z2"]) < 1e-10
+        assert abs(a["log_fidelity"]) < 1e-12
+        psi = m.to_statevector()
+        assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < 1e-10
+    # bond spectra equal the Schmidt values of the exact state in chain order
+    chain = _perm_statevector(g, m.pos, sv.psi)
+    dims = [g.block_dim(b) for b in m.pos]
+    for bond in range(1, len(dims)):
+        left = int(np.prod(dims[:bond]))
+        ref = np.linalg.svd(chain.reshape(left, -1), compute_uv=False)
+        got = m.bond_spectrum(bond)
+        k = min(len(ref), len(got))
+        assert np.max(np.abs(ref[:k] - got[:k])) < 1e-10
+        assert np.all(ref[k:] < 1e-10) and np.all(got[k:] < 1e-10)
+
+
+def test_t4_translation_invariance_full_chi():
+    g = Grid(3, 4)
+    m = mps.BlockMPS(g, 64, 0.5, J, H, DT)
+    for _ in range(3):
+        m.step()
+    psi = m.to_statevector()
+    p = np.abs(psi) ** 2
+    z = statevector.z_table(g.n).astype(np.float64) @ p
+    assert np.max(z) - np.min(z) < 1e-10
+
+
+def test_t5_truncation_fidelity_is_overlap():
+    """A truncation splits the state into kept and discarded orthogonal parts
+    with weights f and 1-f: |<exact|truncated>|^2 = f."""
+    g = Grid(4, 4)
+    m = mps.BlockMPS(g, 6, 0.5, J, H, DT)
+    ops = step_ops(g, list(m.pos))
+    found = False
+    for op in ops:
+        if op[0] != "U2":
+            m.apply_u1(op[1], m._single_site_gate(op[3], op[2]))
+            continue
+        exact = copy.deepcopy(m)
+        exact.chi = 10 ** 6
+        exact.apply_u2(op[1], bool(op[2]), bool(op[3]))
+        f = m.apply_u2(op[1], bool(op[2]), bool(op[3]))
+        if f < 1 - 1e-9:
+            pe, pt = exact.to_statevector(), m.to_statevector()
+            assert abs(np.vdot(pt, pt) - 1) < 1e-12
+            assert abs(abs(np.vdot(pe, pt)) ** 2 - f) < 1e-12
+            found = True
+            break
+    assert found
+
+
+def test_t6_norm_and_monotone_fidelity():
+    g = Grid(4, 4)
+    m = mps.BlockMPS(g, 12, 0.5, J, H, DT)
+    last = 0.0
+    for _ in range(4):
+        m.step()
+        assert m.log_fidelity <= last + 1e-15
+        last = m.log_fidelity
+    assert all(abs(u["norm2"] - 1) < 1e-12 for u in m.update_log)
+    assert 0 < math.exp(m.log_fidelity) <= 1
+
+
+def test_t7_bounds_and_measure_matches_dense():
+    g = Grid(4, 4)
+    m = mps.BlockMPS(g, 8, 1.1, J, H, DT)
+    zt = statevector.z_table(g.n).sum(axis=0).astype(np.float64)
+    for _ in range(4):
+        m.step()
+        o = m.measure()
+        assert abs(o["z"]) <= 1 and o["z"] ** 2 <= o["z2"] + 1e-15 and o["z2"] <= 1
+        p = np.abs(m.to_statevector()) ** 2
+        assert abs(o["z"] - p @ zt / (g.n * p.sum())) < 1e-12
+        assert abs(o["z2"] - p @ (zt * zt) / (g.n ** 2 * p.sum())) < 1e-12
+
+
+@pytest.mark.parametrize("R,C", [(4, 4), (4, 5), (5, 5), (5, 6), (6, 6), (6, 8), (7, 8),
+                                 (3, 3), (2, 4), (1, 4), (3, 2)])
+def test_schedule_gates_each_coupled_pair_once(R, C):
+    g = Grid(R, C)
+    pos = g.snake()
+    for _ in range(2):
+        ops = step_ops(g, pos)
+        gated = [frozenset((o[4], o[5])) for o in ops if o[0] == "U2" and o[3]]
+        coupled = {frozenset((a, b)) for a in range(g.n_blocks)
+                   for b in range(a + 1, g.n_blocks) if pair_coupled(g, a, b)}
+        assert len(gated) == len(set(gated))
+        assert set(gated) == coupled
+    nu2 = sum(1 for o in step_ops(g, g.snake()) if o[0] == "U2")
+    if R >= 3:
+        assert nu2 == 11 * R - 12
+
+
+@pytest.mark.parametrize("line", [l for l in open(
+    __file__.replace("test_oracle_pins.py", "golden/gamma_fit.txt")) if l.strip()
+    and not l.startswith("#")])
+def test_t9_gamma_fit_golden(line):
+    label, dth, x, expected, tol = line.split()
+    n = 16
+    chi = 2 ** (float(x) * n)
+    got = estimators.gamma_fit(float(dth), int(round(chi)), n)
+    assert abs(got - float(expected)) <= float(tol)
+
+
+# --------------------------------------------------------------------------
+# planted mistakes: each must make at least one pin above fail
+def _t4_error():
+    g = Grid(3, 4)       # equal block widths: a missing transpose stays shape-valid
+    m = mps.BlockMPS(g, 64, 0.6, J, H, DT)
+    sv = statevector.StateVector(g, 0.6, J, H, DT)
+    err = 0.0
+    for _ in range(2):
+        m.step()
+        sv.step()
+        a, b = m.measure(), sv.measure()
+        err = max(err, abs(a["z"] - b["z"]), abs(a["z2"] - b["z2"]))
+    return err
+
+
+def test_planted_sign_error_is_caught(monkeypatch):
+    from oracle import lattice
+    orig = lattice.pair_phase
+    monkeypatch.setattr(mps, "pair_phase",
+                        lambda g, a, b, Jx, dt: orig(g, a, b, -Jx, dt))
+    assert _t4_error() > 1e-6
+
+
+def test_planted_missing_swap_is_caught(monkeypatch):
+    orig = mps.BlockMPS.apply_u2
+
+    def bad(self, i, swap, gate):
+        f = orig(self, i, False, gate)
+        if swap:
+            self.pos[i], self.pos[i + 1] = self.pos[i + 1], self.pos[i]
+        return f
+    monkeypatch.setattr(mps.BlockMPS, "apply_u2", bad)
+    assert _t4_error() > 1e-6
