@@ -1,0 +1,53 @@
+// Complex float64 GEMM on gfx950 MFMA (v_mfma_f64_16x16x4f64).
+#pragma once
+#include "common.h"
+
+namespace mpsim {
+
+// Logical operand: element (i, k) = trans ? p[k*ld + i] : p[i*ld + k], optionally conjugated.
+struct ZOp {
+  const cplx* p;
+  long ld;
+  long stride;  // batch stride (elements)
+  int trans;
+  int conj;
+};
+
+enum { EPI_STORE = 0, EPI_THETA = 1 };
+
+struct ZGemm {
+  int M, N, K, batch;
+  ZOp A, B;
+  cplx* C;
+  long ldc, strideC;
+  int transC;       // logical (i, j) stored at transC ? C[j*ldc + i] : C[i*ldc + j]
+  cplx alpha, beta;
+  int lower_only;   // skip output tiles strictly above the diagonal
+  int epi;          // EPI_STORE or EPI_THETA
+  // theta epilogue: row = a*d1 + s1, col = s2*b2 + g; value *= phase[s1][s2]
+  // (phase_trans: phase[s2][s1]); swap: store at (a*d2 + s2, s1*b2 + g), ld d1*b2
+  const cplx* phase;
+  int phase_trans, d1, d2, b2, swap;
+};
+
+// C = alpha*op(A)*op(B) + beta*C (or the theta epilogue). `partial` is a
+// workspace of at least `partial_elems` complex values used for split-K on
+// skinny outputs (may be NULL to disable split-K).
+void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s);
+
+inline ZGemm zgemm_args(int M, int N, int K, ZOp A, ZOp B, cplx* C, long ldc, int transC,
+                        cplx alpha, cplx beta) {
+  ZGemm g{};
+  g.M = M; g.N = N; g.K = K; g.batch = 1;
+  g.A = A; g.B = B; g.C = C; g.ldc = ldc; g.transC = transC;
+  g.alpha = alpha; g.beta = beta;
+  g.epi = EPI_STORE;
+  return g;
+}
+
+inline ZOp zop(const cplx* p, long ld, int trans, int conj = 0) {
+  ZOp o{p, ld, 0, trans, conj};
+  return o;
+}
+
+}  // namespace mpsim

@@ -1,0 +1,80 @@
+// Dense float64 linear algebra for the truncation step: Hermitian
+// eigenvectors of the top-q eigenspace (Householder tridiagonalisation,
+// bisection, inverse iteration, orthonormalisation, back-transformation) and
+// Householder QR for moving the orthogonality centre.
+#pragma once
+#include "common.h"
+#include "gemm.h"
+
+namespace mpsim {
+
+constexpr int TRD_NB = 32, QR_NB = 32, BT_NB = 64;
+
+struct LinalgWork {
+  long nmax = 0, qmax = 0, mmax = 0;  // eig dim, wanted count, QR rows
+  cplx* W = nullptr;        // nmax x TRD_NB (col-major, ld nmax)
+  cplx* tpart = nullptr;    // partial sums (column step reductions)
+  long tpart_elems = 0;
+  cplx* P = nullptr;        // Hermitian mat-vec partials, nt*nt*64
+  long P_elems = 0;
+  double* d = nullptr;      // tridiagonal diagonal (nmax)
+  double* e = nullptr;      // off-diagonal (nmax)
+  cplx* tau = nullptr;      // tridiagonalisation reflector scalars (nmax)
+  cplx* qtau = nullptr;     // QR reflector scalars (max QR columns)
+  double* e2 = nullptr;     // squared off-diagonal (nmax)
+  cplx* dpart = nullptr;    // partial dot products (column steps)
+  double* npart = nullptr;  // partial norms (QR column steps)
+  double* scal = nullptr;   // 16 doubles of scalars
+  double* lam = nullptr;    // eigenvalues (qmax + 1), ascending
+  double* iwork = nullptr;  // inverse-iteration work, 6 * nmax * qmax
+  cplx* T = nullptr;        // block reflector factors, (maxk/QR_NB + 1) * 64 * 64
+  long T_elems = 0;
+  cplx* S = nullptr;        // 64 x 64 scratch
+  cplx* W1 = nullptr;       // 64 x wmax
+  cplx* W2 = nullptr;       // 64 x wmax
+  long wmax = 0;
+  cplx* V = nullptr;        // clean reflector block, vmax x 64 (col-major)
+  long vmax = 0;
+  cplx* gpart = nullptr;    // split-K partials
+  long gpart_elems = 0;
+  int* flag = nullptr;      // numeric failure flag (device)
+};
+
+// Reduce Hermitian A (n x n, column-major, lower triangle referenced) to real
+// symmetric tridiagonal form A = Q T Q^H. T goes to w.d / w.e, reflectors
+// stay in the strictly lower part of A (unit entry stored explicitly), their
+// scalars in w.tau.
+void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s);
+
+// Eigenvalues number lo..lo+cnt-1 (ascending, 0-based) of T by bisection.
+void tridiag_eigvals(int n, int lo, int cnt, LinalgWork& w, hipStream_t s);
+
+// Eigenvectors of T for the `q` largest eigenvalues (already in w.lam[1..q]
+// when w.lam[0] holds the (q+1)-th largest, or w.lam[0..q-1] if has_extra=0)
+// by inverse iteration; written as real values into X (n x q row-major,
+// ld ldx), column j for the j-th largest eigenvalue.
+void tridiag_invit(int n, int q, int lam_off, LinalgWork& w, cplx* X, long ldx, uint64_t seed,
+                   hipStream_t s);
+
+// X (n x q row-major) <- Q X with Q from hetrd_lower (reflectors in A).
+void hetrd_backtransform(int n, const cplx* A, long lda, int q, cplx* X, long ldx,
+                         LinalgWork& w, hipStream_t s);
+
+// Householder QR of the m x k matrix with element (r, c) at A[r*rs + c*cs]
+// (either rs == 1 or cs == 1), in place: R in the upper triangle,
+// reflectors below, scalars in w.tau, block factors in w.T.
+void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream_t s);
+// Explicit Q (m x kmin row-major, ld ldq) from a factored matrix.
+void qr_form_q(int m, int k, const cplx* A, long rs, long cs, LinalgWork& w, cplx* Q, long ldq,
+               hipStream_t s);
+// R (kmin x k row-major, ld ldr) from a factored matrix.
+void qr_get_r(int m, int k, const cplx* A, long rs, long cs, cplx* R, long ldr, hipStream_t s);
+
+// Top-q eigenspace of Hermitian G (n x n column-major, overwritten): an
+// orthonormal basis U (n x q row-major, ld ldu) ordered by descending
+// eigenvalue. `Xtmp` is an n x q scratch buffer. Eigenvalues
+// (q + 1 largest if q < n, ascending) are left in w.lam.
+void heev_top(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
+              uint64_t seed, hipStream_t s);
+
+}  // namespace mpsim

@@ -1,0 +1,679 @@
+// Dense float64 linear algebra on gfx950 for the truncation step.
+//
+// The truncation of a two-site block needs an orthonormal basis of the top-q
+// eigenspace of the Gram matrix G = M M^H (or M^H M). Every part runs on the
+// device:
+//   1. blocked Householder reduction of G to real tridiagonal T: per column a
+//      reflector (with the panel's earlier reflectors applied on the fly) and
+//      a Hermitian matrix-vector product on the lower-triangle tiles of the
+//      trailing matrix; per panel of 32 columns a rank-64 update on MFMA;
+//   2. bisection with Sturm counts for the wanted eigenvalues of T;
+//   3. inverse iteration (tridiagonal LU with partial pivoting) for their
+//      eigenvectors, one thread per vector;
+//   4. Householder QR of the vectors (repairs orthogonality inside clusters
+//      of close eigenvalues; only the spanned subspace matters);
+//   5. back-transformation by the tridiagonalisation reflectors in blocks of
+//      64 (compact WY form, MFMA GEMMs).
+// Householder QR (panel column steps + WY trailing updates) also moves the
+// orthogonality centre of the MPS.
+#include "linalg.h"
+
+#include <algorithm>
+#include <cfloat>
+
+namespace mpsim {
+
+// Reflector H = I - tau v v^H with v = [1; x*scale] such that
+// H^H [alpha; x] = [beta; 0], beta real.
+__device__ inline void reflector(cplx alpha, double xnorm2, double& beta, cplx& tau, cplx& scale) {
+  if (xnorm2 == 0.0 && alpha.y == 0.0) {
+    beta = alpha.x;
+    tau = make_double2(0.0, 0.0);
+    scale = make_double2(0.0, 0.0);
+    return;
+  }
+  double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+  beta = (alpha.x >= 0.0) ? -nrm : nrm;
+  tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+  scale = cinv(make_double2(alpha.x - beta, alpha.y));
+}
+
+__device__ inline cplx wave_csum(cplx v) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  return v;
+}
+
+static ZOp strided_op(const cplx* base, long rs, long cs, int conj = 0) {
+  if (cs == 1) return zop(base, rs, 0, conj);
+  return zop(base, cs, 1, conj);
+}
+
+// ---------------------------------------------------------------------------
+// Tridiagonalisation (lower), panel of TRD_NB columns
+#define TP (2 * TRD_NB + 1)
+
+__global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, const cplx* W, long ldw,
+                                                 int i0, int j, int c, cplx* tpart) {
+  __shared__ cplx wrow[TRD_NB], vrow[TRD_NB];
+  const int t = threadIdx.x;
+  if (t < j) {
+    wrow[t] = cconj(W[(long)t * ldw + c]);
+    vrow[t] = cconj(A[(long)(i0 + t) * lda + c]);
+  }
+  __syncthreads();
+  const long r = c + (long)blockIdx.x * 256 + t;
+  cplx a = make_double2(0.0, 0.0);
+  if (r < n) {
+    a = A[(long)c * lda + r];
+    for (int jj = 0; jj < j; ++jj) {
+      cplx v = A[(long)(i0 + jj) * lda + r];
+      cplx wv = W[(long)jj * ldw + r];
+      a = csub(a, cadd(cmul(v, wrow[jj]), cmul(wv, vrow[jj])));
+    }
+    if (r == c) a.y = 0.0;
+    A[(long)c * lda + r] = a;
+  }
+  const bool act = (r < n) && (r >= c + 2);
+  const int lane = t & 63, wv = t >> 6;
+  const long base = ((long)blockIdx.x * 4 + wv) * TP;
+  double nn = wave_sum(act ? cabs2(a) : 0.0);
+  if (lane == 0) tpart[base] = make_double2(nn, 0.0);
+  for (int jj = 0; jj < j; ++jj) {
+    cplx tw = make_double2(0.0, 0.0), tv = make_double2(0.0, 0.0);
+    if (act) {
+      tw = cmulc(W[(long)jj * ldw + r], a);
+      tv = cmulc(A[(long)(i0 + jj) * lda + r], a);
+    }
+    tw = wave_csum(tw);
+    tv = wave_csum(tv);
+    if (lane == 0) {
+      tpart[base + 1 + jj] = tw;
+      tpart[base + 1 + TRD_NB + jj] = tv;
+    }
+  }
+}
+
+__device__ inline cplx trd_v(const cplx* A, long lda, int n, int c, long r, cplx sc) {
+  if (r >= n) return make_double2(0.0, 0.0);
+  if (r == c + 1) return make_double2(1.0, 0.0);
+  return cmul(A[(long)c * lda + r], sc);
+}
+
+// y = A22 v over the lower-triangle tiles of the trailing matrix.
+__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, int c,
+                                                  const cplx* tpart, int nparts, cplx* P, int nt,
+                                                  double* scal) {
+  __shared__ cplx vI[64], vJ[64];
+  __shared__ cplx red[4][64];
+  __shared__ double sh[5];
+  const int t = threadIdx.x;
+  const long k = blockIdx.x;
+  long I = (long)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > k) --I;
+  while ((I + 1) * (I + 2) / 2 <= k) ++I;
+  const long J = k - I * (I + 1) / 2;
+  const int o = c + 1;
+  if (t == 0) {
+    double xn = 0.0;
+    for (int p = 0; p < nparts; ++p) xn += tpart[(long)p * TP].x;
+    cplx alpha = A[(long)c * lda + o];
+    double beta;
+    cplx tau, sc;
+    reflector(alpha, xn, beta, tau, sc);
+    sh[0] = beta; sh[1] = tau.x; sh[2] = tau.y; sh[3] = sc.x; sh[4] = sc.y;
+    if (blockIdx.x == 0)
+      for (int u = 0; u < 5; ++u) scal[u] = sh[u];
+  }
+  __syncthreads();
+  const cplx sc = make_double2(sh[3], sh[4]);
+  if (t < 64) vI[t] = trd_v(A, lda, n, c, o + I * 64 + t, sc);
+  else if (t < 128) vJ[t - 64] = trd_v(A, lda, n, c, o + J * 64 + (t - 64), sc);
+  __syncthreads();
+  const int rr = t & 63, cg = t >> 6;
+  const long row = o + I * 64 + rr;
+  cplx y = make_double2(0.0, 0.0);
+  for (int cc = 0; cc < 16; ++cc) {
+    const int cl = cg * 16 + cc;
+    const long col = o + J * 64 + cl;
+    cplx a = make_double2(0.0, 0.0);
+    const bool in = row < n && col < n;
+    if (I == J) {
+      if (in) {
+        if (cl < rr) a = A[col * lda + row];
+        else if (cl > rr) a = cconj(A[row * lda + col]);
+        else a = make_double2(A[col * lda + row].x, 0.0);
+      }
+      y = cadd(y, cmul(a, vJ[cl]));
+    } else {
+      if (in) a = A[col * lda + row];
+      y = cadd(y, cmul(a, vJ[cl]));
+      cplx z = wave_csum(cmulc(a, vI[rr]));
+      if (rr == 0) P[(J * nt + I) * 64 + cl] = z;
+    }
+  }
+  red[cg][rr] = y;
+  __syncthreads();
+  if (t < 64) {
+    cplx s = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
+    P[(I * nt + J) * 64 + t] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trd_w(int n, cplx* A, long lda, cplx* W, long ldw, int i0,
+                                               int j, int c, const cplx* tpart, int nparts,
+                                               const cplx* P, int nt, const double* scal,
+                                               cplx* dpart, double* d, double* e, cplx* tau) {
+  __shared__ cplx t1[TRD_NB], t2[TRD_NB];
+  const int t = threadIdx.x;
+  const int o = c + 1;
+  const cplx tauv = make_double2(scal[1], scal[2]);
+  const cplx sc = make_double2(scal[3], scal[4]);
+  if (t < j) {
+    cplx s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+    for (int p = 0; p < nparts; ++p) {
+      s1 = cadd(s1, tpart[(long)p * TP + 1 + t]);
+      s2 = cadd(s2, tpart[(long)p * TP + 1 + TRD_NB + t]);
+    }
+    t1[t] = cadd(cconj(W[(long)t * ldw + o]), cmul(sc, s1));
+    t2[t] = cadd(cconj(A[(long)(i0 + t) * lda + o]), cmul(sc, s2));
+  }
+  __syncthreads();
+  const long r = o + (long)blockIdx.x * 256 + t;
+  cplx y = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+  if (r < n) {
+    const long I = (r - o) / 64, x = (r - o) % 64;
+    for (long Jb = 0; Jb < nt; ++Jb) y = cadd(y, P[(I * nt + Jb) * 64 + x]);
+    for (int jj = 0; jj < j; ++jj)
+      y = csub(y, cadd(cmul(A[(long)(i0 + jj) * lda + r], t1[jj]), cmul(W[(long)jj * ldw + r], t2[jj])));
+    y = cmul(tauv, y);
+    W[(long)j * ldw + r] = y;
+    v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
+    A[(long)c * lda + r] = v;
+  }
+  cplx dt = wave_csum(cmulc(y, v));
+  if ((t & 63) == 0) dpart[(long)blockIdx.x * 4 + (t >> 6)] = dt;
+  if (blockIdx.x == 0 && t == 0) {
+    tau[c] = tauv;
+    e[c] = scal[0];
+    d[c] = A[(long)c * lda + c].x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trd_w2(int n, const cplx* A, long lda, cplx* W, long ldw,
+                                                int j, int c, const cplx* dpart, int ndp,
+                                                const double* scal) {
+  __shared__ cplx alpha_s;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    cplx dsum = make_double2(0.0, 0.0);
+    for (int p = 0; p < ndp; ++p) dsum = cadd(dsum, dpart[p]);
+    const cplx tauv = make_double2(scal[1], scal[2]);
+    alpha_s = cscale(cmul(tauv, dsum), -0.5);
+  }
+  __syncthreads();
+  const long r = c + 1 + (long)blockIdx.x * 256 + t;
+  if (r < n) W[(long)j * ldw + r] = cadd(W[(long)j * ldw + r], cmul(alpha_s, A[(long)c * lda + r]));
+}
+
+__global__ void k_trd_last(int n, const cplx* A, long lda, double* d) {
+  d[n - 1] = A[(long)(n - 1) * lda + (n - 1)].x;
+}
+
+void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
+  const long ldw = w.nmax;
+  for (int i0 = 0; i0 < n - 1; i0 += TRD_NB) {
+    const int ib = std::min(TRD_NB, n - 1 - i0);
+    for (int j = 0; j < ib; ++j) {
+      const int c = i0 + j;
+      const int nb1 = ceil_div(n - c, 256);
+      hipLaunchKernelGGL(k_trd_col, dim3(nb1), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c, w.tpart);
+      const int np = n - c - 1;
+      const int nt = ceil_div(np, 64);
+      const long ntiles = (long)nt * (nt + 1) / 2;
+      hipLaunchKernelGGL(k_trd_hemv, dim3((unsigned)ntiles), dim3(256), 0, s, n, (const cplx*)A, lda,
+                         c, (const cplx*)w.tpart, nb1 * 4, w.P, nt, w.scal);
+      const int nb4 = ceil_div(np, 256);
+      hipLaunchKernelGGL(k_trd_w, dim3(nb4), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c,
+                         (const cplx*)w.tpart, nb1 * 4, (const cplx*)w.P, nt, (const double*)w.scal,
+                         w.dpart, w.d, w.e, w.tau);
+      hipLaunchKernelGGL(k_trd_w2, dim3(nb4), dim3(256), 0, s, n, (const cplx*)A, lda, w.W, ldw, j, c,
+                         (const cplx*)w.dpart, nb4 * 4, (const double*)w.scal);
+    }
+    const int o2 = i0 + ib;
+    if (o2 < n) {
+      const int nn = n - o2;
+      cplx* C = A + (long)o2 * lda + o2;
+      // C -= V W^H
+      ZGemm g1 = zgemm_args(nn, nn, ib, zop(A + (long)i0 * lda + o2, lda, 1),
+                            zop(w.W + o2, ldw, 0, 1), C, lda, 1, make_double2(-1.0, 0.0),
+                            make_double2(1.0, 0.0));
+      g1.lower_only = 1;
+      zgemm(g1, nullptr, 0, s);
+      // C -= W V^H
+      ZGemm g2 = zgemm_args(nn, nn, ib, zop(w.W + o2, ldw, 1),
+                            zop(A + (long)i0 * lda + o2, lda, 0, 1), C, lda, 1,
+                            make_double2(-1.0, 0.0), make_double2(1.0, 0.0));
+      g2.lower_only = 1;
+      zgemm(g2, nullptr, 0, s);
+    }
+  }
+  hipLaunchKernelGGL(k_trd_last, dim3(1), dim3(1), 0, s, n, (const cplx*)A, lda, w.d);
+}
+
+// ---------------------------------------------------------------------------
+// Tridiagonal eigenvalues (bisection) and eigenvectors (inverse iteration)
+
+// bounds[0] = Gershgorin lower, [1] = upper, [2] = norm estimate, [3] = pivmin
+__global__ __launch_bounds__(256) void k_trd_prep(int n, const double* d, const double* e, double* e2,
+                                                  double* bounds) {
+  __shared__ double sh[8];
+  double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
+    double ep = (i < n - 1) ? fabs(e[i]) : 0.0;
+    lo = fmin(lo, d[i] - em - ep);
+    hi = fmax(hi, d[i] + em + ep);
+    if (i < n - 1) {
+      e2[i] = e[i] * e[i];
+      emax = fmax(emax, e[i] * e[i]);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+    emax = fmax(emax, __shfl_xor(emax, off, 64));
+  }
+  __shared__ double slo[4], shi[4], sem[4];
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { slo[w] = lo; shi[w] = hi; sem[w] = emax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      slo[0] = fmin(slo[0], slo[k]);
+      shi[0] = fmax(shi[0], shi[k]);
+      sem[0] = fmax(sem[0], sem[k]);
+    }
+    double tn = fmax(fabs(slo[0]), fabs(shi[0]));
+    double pad = 2.0 * DBL_EPSILON * tn + 4.0 * DBL_MIN;
+    bounds[0] = slo[0] - pad;
+    bounds[1] = shi[0] + pad;
+    bounds[2] = tn;
+    bounds[3] = DBL_MIN * fmax(1.0, sem[0]);
+    (void)sh;
+  }
+}
+
+__device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) <= pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ void k_bisect(int n, const double* d, const double* e2, int lo, int cnt,
+                         const double* bounds, double* lam) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cnt) return;
+  const int idx = lo + k;
+  double a = bounds[0], b = bounds[1];
+  const double atol = DBL_EPSILON * bounds[2], pivmin = bounds[3];
+  for (int it = 0; it < 256; ++it) {
+    if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + atol) break;
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    if (sturm_count(n, d, e2, mid, pivmin) > idx) b = mid;
+    else a = mid;
+  }
+  lam[k] = 0.5 * (a + b);
+}
+
+__device__ inline double hash_uniform(uint64_t seed, uint64_t a, uint64_t b) {
+  uint64_t z = seed ^ (a * 0x9E3779B97F4A7C15ULL) ^ (b * 0xC2B2AE3D27D4EB4FULL);
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+}
+
+// One thread per wanted eigenvector; work arrays interleaved [i*q + kq].
+__global__ void k_invit(int n, const double* d, const double* e, int q, const double* lam,
+                        int lam_off, const double* bounds, double* work, cplx* X, long ldx,
+                        uint64_t seed) {
+  const int kq = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kq >= q) return;
+  const long nq = (long)n * q;
+  double* dl = work;
+  double* dd = work + nq;
+  double* du = work + 2 * nq;
+  double* du2 = work + 3 * nq;
+  double* xx = work + 4 * nq;
+  double* pv = work + 5 * nq;
+#define AT(arr, i) arr[(long)(i) * q + kq]
+  const double lmb = lam[lam_off + q - 1 - kq];
+  double epsp = DBL_EPSILON * bounds[2];
+  if (epsp == 0.0) epsp = DBL_MIN;
+  for (int i = 0; i < n; ++i) {
+    AT(dd, i) = d[i] - lmb;
+    if (i < n - 1) {
+      AT(dl, i) = e[i];
+      AT(du, i) = e[i];
+      AT(du2, i) = 0.0;
+    }
+  }
+  // LU with partial pivoting of the tridiagonal T - lmb I
+  for (int i = 0; i < n - 1; ++i) {
+    const double di = AT(dd, i), li = AT(dl, i);
+    if (fabs(di) >= fabs(li)) {
+      double fact = (di != 0.0) ? li / di : 0.0;
+      AT(dl, i) = fact;
+      AT(dd, i + 1) = AT(dd, i + 1) - fact * AT(du, i);
+      AT(pv, i) = 0.0;
+    } else {
+      const double fact = di / li;
+      AT(dd, i) = li;
+      AT(dl, i) = fact;
+      const double tmp = AT(du, i);
+      const double dnext = AT(dd, i + 1);
+      AT(du, i) = dnext;
+      AT(dd, i + 1) = tmp - fact * dnext;
+      if (i < n - 2) {
+        AT(du2, i) = AT(du, i + 1);
+        AT(du, i + 1) = -fact * AT(du, i + 1);
+      }
+      AT(pv, i) = 1.0;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (fabs(AT(dd, i)) < epsp) AT(dd, i) = (AT(dd, i) < 0.0) ? -epsp : epsp;
+  for (int i = 0; i < n; ++i) AT(xx, i) = hash_uniform(seed, (uint64_t)kq, (uint64_t)i);
+  double nrm = 1.0;
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 0; i < n - 1; ++i) {
+      if (AT(pv, i) == 0.0) {
+        AT(xx, i + 1) = AT(xx, i + 1) - AT(dl, i) * AT(xx, i);
+      } else {
+        const double tmp = AT(xx, i);
+        AT(xx, i) = AT(xx, i + 1);
+        AT(xx, i + 1) = tmp - AT(dl, i) * AT(xx, i);
+      }
+    }
+    AT(xx, n - 1) = AT(xx, n - 1) / AT(dd, n - 1);
+    if (n > 1) AT(xx, n - 2) = (AT(xx, n - 2) - AT(du, n - 2) * AT(xx, n - 1)) / AT(dd, n - 2);
+    for (int i = n - 3; i >= 0; --i)
+      AT(xx, i) = (AT(xx, i) - AT(du, i) * AT(xx, i + 1) - AT(du2, i) * AT(xx, i + 2)) / AT(dd, i);
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(AT(xx, i)));
+    if (!(mx > 0.0) || !isfinite(mx)) mx = 1.0;
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = AT(xx, i) / mx;
+      AT(xx, i) = v;
+      s2 += v * v;
+    }
+    nrm = sqrt(s2);
+    if (!(nrm > 0.0)) nrm = 1.0;
+    for (int i = 0; i < n; ++i) AT(xx, i) = AT(xx, i) / nrm;
+  }
+  for (int i = 0; i < n; ++i) X[(long)i * ldx + kq] = make_double2(AT(xx, i), 0.0);
+#undef AT
+}
+
+void tridiag_eigvals(int n, int lo, int cnt, LinalgWork& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_trd_prep, dim3(1), dim3(256), 0, s, n, (const double*)w.d, (const double*)w.e,
+                     w.e2, w.scal + 8);
+  hipLaunchKernelGGL(k_bisect, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, n, (const double*)w.d,
+                     (const double*)w.e2, lo, cnt, (const double*)(w.scal + 8), w.lam);
+}
+
+void tridiag_invit(int n, int q, int lam_off, LinalgWork& w, cplx* X, long ldx, uint64_t seed,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_invit, dim3(ceil_div(q, 64)), dim3(64), 0, s, n, (const double*)w.d,
+                     (const double*)w.e, q, (const double*)w.lam, lam_off,
+                     (const double*)(w.scal + 8), w.iwork, X, ldx, seed);
+}
+
+// ---------------------------------------------------------------------------
+// Block reflectors
+
+// V (mrows x ib, column-major ld ldv): unit lower trapezoidal from the
+// reflectors stored at A[row0 + rr, col0 + jj].
+__global__ void k_extract_v(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib,
+                            cplx* V, long ldv) {
+  const long total = (long)mrows * ib;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long rr = idx % mrows, jj = idx / mrows;
+    cplx v;
+    if (rr < jj) v = make_double2(0.0, 0.0);
+    else if (rr == jj) v = make_double2(1.0, 0.0);
+    else v = A[(row0 + rr) * rs + (col0 + jj) * cs];
+    V[jj * ldv + rr] = v;
+  }
+}
+
+// Forward column-wise block reflector factor: T upper (ib x ib, row-major
+// ld 64) with H_0 ... H_{ib-1} = I - V T V^H, from S = V^H V and tau.
+__global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx* tau, cplx* T) {
+  __shared__ cplx tcol[64];
+  const int i = threadIdx.x;
+  for (int r = 0; r < 64; ++r) T[r * 64 + i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < ib; ++j) {
+    const cplx mt = cscale(tau[j], -1.0);
+    cplx acc = make_double2(0.0, 0.0);
+    if (i < j)
+      for (int l = i; l < j; ++l) acc = cadd(acc, cmul(T[i * 64 + l], cmul(mt, S[l * 64 + j])));
+    tcol[i] = acc;
+    __syncthreads();
+    if (i < j) T[i * 64 + j] = tcol[i];
+    if (i == j) T[j * 64 + j] = tau[j];
+    __syncthreads();
+  }
+}
+
+static void block_reflector(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib,
+                            const cplx* tau, cplx* T, LinalgWork& w, hipStream_t s) {
+  const long ldv = w.vmax;
+  long total = (long)mrows * ib;
+  int blocks = (int)std::min<long>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_extract_v, dim3(blocks), dim3(256), 0, s, A, rs, cs, row0, col0, mrows, ib,
+                     w.V, ldv);
+  // S = V^H V (ib x ib, ld 64)
+  ZGemm g = zgemm_args(ib, ib, mrows, zop(w.V, ldv, 0, 1), zop(w.V, ldv, 1), w.S, 64, 0,
+                       make_double2(1.0, 0.0), make_double2(0.0, 0.0));
+  zgemm(g, w.gpart, w.gpart_elems, s);
+  hipLaunchKernelGGL(k_larft, dim3(1), dim3(64), 0, s, ib, (const cplx*)w.S, tau, T);
+}
+
+// Apply (I - V op(T) V^H) to the mrows x ncols block C (element (r, c) at
+// C[r*rs + c*cs]); op(T) = T or T^H. V and T as built by block_reflector.
+static void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, int tconj,
+                                  cplx* C, long rs, long cs, LinalgWork& w, hipStream_t s) {
+  if (ncols <= 0 || mrows <= 0) return;
+  const long ldv = w.vmax;
+  const cplx one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  // W1 = V^H C (ib x ncols, ld wmax)
+  ZGemm g1 = zgemm_args(ib, ncols, mrows, zop(w.V, ldv, 0, 1), strided_op(C, rs, cs), w.W1, w.wmax,
+                        0, one, zero);
+  zgemm(g1, w.gpart, w.gpart_elems, s);
+  // W2 = op(T) W1
+  ZGemm g2 = zgemm_args(ib, ncols, ib, tconj ? zop(T, 64, 1, 1) : zop(T, 64, 0), zop(w.W1, w.wmax, 0),
+                        w.W2, w.wmax, 0, one, zero);
+  zgemm(g2, nullptr, 0, s);
+  // C -= V W2
+  ZOp cop = strided_op(C, rs, cs);
+  ZGemm g3 = zgemm_args(mrows, ncols, ib, zop(w.V, ldv, 1), zop(w.W2, w.wmax, 0), C, cop.ld,
+                        cop.trans, make_double2(-1.0, 0.0), one);
+  zgemm(g3, nullptr, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR
+
+__global__ __launch_bounds__(256) void k_qr_norm(int m, const cplx* A, long rs, long cs, int c,
+                                                 double* npart) {
+  const long r = c + 1 + (long)blockIdx.x * 256 + threadIdx.x;
+  double v = (r < m) ? cabs2(A[r * rs + (long)c * cs]) : 0.0;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) npart[(long)blockIdx.x * 4 + (threadIdx.x >> 6)] = v;
+}
+
+__global__ __launch_bounds__(256) void k_qr_dots(int m, const cplx* A, long rs, long cs, int c, int pe,
+                                                 const double* npart, int nnp, cplx* wpart,
+                                                 double* scal) {
+  __shared__ double sh[5];
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double xn = 0.0;
+    for (int p = 0; p < nnp; ++p) xn += npart[p];
+    double beta;
+    cplx tau, sc;
+    reflector(A[(long)c * rs + (long)c * cs], xn, beta, tau, sc);
+    sh[0] = beta; sh[1] = tau.x; sh[2] = tau.y; sh[3] = sc.x; sh[4] = sc.y;
+    if (blockIdx.x == 0)
+      for (int u = 0; u < 5; ++u) scal[u] = sh[u];
+  }
+  __syncthreads();
+  const cplx sc = make_double2(sh[3], sh[4]);
+  const long r = c + (long)blockIdx.x * 256 + t;
+  cplx v = make_double2(0.0, 0.0);
+  if (r < m) v = (r == c) ? make_double2(1.0, 0.0) : cmul(A[r * rs + (long)c * cs], sc);
+  for (int jj = c + 1; jj < pe; ++jj) {
+    cplx p = (r < m) ? cmulc(v, A[r * rs + (long)jj * cs]) : make_double2(0.0, 0.0);
+    p = wave_csum(p);
+    if ((t & 63) == 0) wpart[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + (jj - c - 1)] = p;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_qr_apply(int m, cplx* A, long rs, long cs, int c, int pe,
+                                                  const cplx* wpart, int nwp, const double* scal,
+                                                  double* npart, cplx* tau_out) {
+  __shared__ cplx wj[QR_NB];
+  const int t = threadIdx.x;
+  if (t < pe - c - 1) {
+    cplx s = make_double2(0.0, 0.0);
+    for (int p = 0; p < nwp; ++p) s = cadd(s, wpart[(long)p * QR_NB + t]);
+    wj[t] = s;
+  }
+  __syncthreads();
+  const double beta = scal[0];
+  const cplx tau = make_double2(scal[1], scal[2]), sc = make_double2(scal[3], scal[4]);
+  const cplx ctau = cconj(tau);
+  const long r = c + (long)blockIdx.x * 256 + t;
+  double nn = 0.0;
+  if (r < m) {
+    const cplx v = (r == c) ? make_double2(1.0, 0.0) : cmul(A[r * rs + (long)c * cs], sc);
+    for (int jj = c + 1; jj < pe; ++jj) {
+      cplx a = csub(A[r * rs + (long)jj * cs], cmul(ctau, cmul(v, wj[jj - c - 1])));
+      A[r * rs + (long)jj * cs] = a;
+      if (jj == c + 1 && r >= c + 2) nn = cabs2(a);
+    }
+    A[r * rs + (long)c * cs] = (r == c) ? make_double2(beta, 0.0) : v;
+  }
+  nn = wave_sum(nn);
+  if ((t & 63) == 0) npart[(long)blockIdx.x * 4 + (t >> 6)] = nn;
+  if (blockIdx.x == 0 && t == 0) tau_out[c] = tau;
+}
+
+void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream_t s) {
+  const int kmin = std::min(m, k);
+  cplx* wpart = w.tpart;
+  for (int p0 = 0, panel = 0; p0 < kmin; p0 += QR_NB, ++panel) {
+    const int pe = std::min(p0 + QR_NB, kmin);
+    int nb0 = std::max(1, ceil_div(m - p0 - 1, 256));
+    hipLaunchKernelGGL(k_qr_norm, dim3(nb0), dim3(256), 0, s, m, (const cplx*)A, rs, cs, p0, w.npart);
+    int nnp = nb0 * 4;
+    for (int c = p0; c < pe; ++c) {
+      const int nbr = ceil_div(m - c, 256);
+      hipLaunchKernelGGL(k_qr_dots, dim3(nbr), dim3(256), 0, s, m, (const cplx*)A, rs, cs, c, pe,
+                         (const double*)w.npart, nnp, wpart, w.scal);
+      hipLaunchKernelGGL(k_qr_apply, dim3(nbr), dim3(256), 0, s, m, A, rs, cs, c, pe,
+                         (const cplx*)wpart, nbr * 4, (const double*)w.scal, w.npart, w.qtau);
+      nnp = nbr * 4;
+    }
+    const int ib = pe - p0;
+    cplx* T = w.T + (long)panel * 4096;
+    block_reflector(A, rs, cs, p0, p0, m - p0, ib, w.qtau + p0, T, w, s);
+    if (pe < k)
+      apply_block_reflector(m - p0, k - pe, ib, T, 1, A + (long)p0 * rs + (long)pe * cs, rs, cs, w, s);
+  }
+}
+
+__global__ void k_set_identity(int m, int k, cplx* Q, long ldq) {
+  const long total = (long)m * k;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long r = idx / k, c = idx % k;
+    Q[r * ldq + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+}
+
+void qr_form_q(int m, int k, const cplx* A, long rs, long cs, LinalgWork& w, cplx* Q, long ldq,
+               hipStream_t s) {
+  const int kmin = std::min(m, k);
+  long total = (long)m * kmin;
+  int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_set_identity, dim3(blocks), dim3(256), 0, s, m, kmin, Q, ldq);
+  const int npanels = ceil_div(kmin, QR_NB);
+  for (int panel = npanels - 1; panel >= 0; --panel) {
+    const int p0 = panel * QR_NB, pe = std::min(p0 + QR_NB, kmin), ib = pe - p0;
+    const cplx* T = w.T + (long)panel * 4096;
+    long tv = (long)(m - p0) * ib;
+    int bl = (int)std::min<long>((tv + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_extract_v, dim3(bl), dim3(256), 0, s, A, rs, cs, p0, p0, m - p0, ib, w.V,
+                       (long)w.vmax);
+    apply_block_reflector(m - p0, kmin - p0, ib, T, 0, Q + (long)p0 * ldq + p0, ldq, 1, w, s);
+  }
+}
+
+__global__ void k_get_r(int m, int k, const cplx* A, long rs, long cs, cplx* R, long ldr) {
+  const int kmin = m < k ? m : k;
+  const long total = (long)kmin * k;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long i = idx / k, j = idx % k;
+    R[i * ldr + j] = (j >= i) ? A[i * rs + j * cs] : make_double2(0.0, 0.0);
+  }
+}
+
+void qr_get_r(int m, int k, const cplx* A, long rs, long cs, cplx* R, long ldr, hipStream_t s) {
+  long total = (long)std::min(m, k) * k;
+  int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_get_r, dim3(std::max(blocks, 1)), dim3(256), 0, s, m, k, A, rs, cs, R, ldr);
+}
+
+// ---------------------------------------------------------------------------
+
+void hetrd_backtransform(int n, const cplx* A, long lda, int q, cplx* X, long ldx, LinalgWork& w,
+                         hipStream_t s) {
+  const int nref = n - 1;
+  if (nref <= 0) return;
+  const int ngroups = ceil_div(nref, BT_NB);
+  for (int gi = ngroups - 1; gi >= 0; --gi) {
+    const int c0 = gi * BT_NB, ib = std::min(BT_NB, nref - c0);
+    const int mrows = n - (c0 + 1);
+    block_reflector(A, 1, lda, c0 + 1, c0, mrows, ib, w.tau + c0, w.T, w, s);
+    apply_block_reflector(mrows, q, ib, w.T, 0, X + (long)(c0 + 1) * ldx, ldx, 1, w, s);
+  }
+}
+
+void heev_top(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
+              uint64_t seed, hipStream_t s) {
+  hetrd_lower(n, G, ldg, w, s);
+  const int extra = (q < n) ? 1 : 0;
+  tridiag_eigvals(n, n - q - extra, q + extra, w, s);
+  tridiag_invit(n, q, extra, w, Xtmp, q, seed, s);
+  qr_factor(n, q, Xtmp, q, 1, w, s);
+  qr_form_q(n, q, Xtmp, q, 1, w, U, ldu, s);
+  hetrd_backtransform(n, G, ldg, q, U, ldu, w, s);
+}
+
+}  // namespace mpsim

@@ -1,0 +1,26 @@
+// Element-wise and reduction kernels of the block-MPS update and measurement.
+#pragma once
+#include "common.h"
+
+namespace mpsim {
+
+// A[a, s, b] <- sum_t U[s, t] A[a, t, b] for a site of shape (b0, d, b1).
+void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream_t s);
+// dst[slot] = sum |x|^2 over len entries (deterministic two-pass reduction).
+void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStream_t s);
+// Truncation bookkeeping: f = sc[3]/sc[2], sc[0] += log f, sc[4] = 1/sqrt(sc[3]),
+// log entry idx gets (f, gap); gap from the ascending eigenvalues lam.
+void launch_trunc_finalize(double* sc, double* flog, long idx, const double* lam, int q, int extra,
+                           int* flag, hipStream_t s);
+// x *= sc[4]
+void launch_scale_by(cplx* x, long len, const double* sc, hipStream_t s);
+// dst (cols x rows, ld ldd) = conj(src)^T, src rows x cols (ld lds)
+void launch_conj_transpose(const cplx* src, int rows, int cols, long lds, cplx* dst, long ldd,
+                           hipStream_t s);
+// measurement: X holds 3 stacked blocks of b x (d*b2); Y1 = X1 + z X0,
+// Y2 = X2 + 2 z X1 + z^2 X0 with z = zsum[s] on the physical index.
+void launch_meas_combine(cplx* X, int b, int d, int b2, const double* zsum, hipStream_t s);
+void launch_env_init(cplx* E, hipStream_t s);
+void launch_fill(cplx* x, long len, cplx v, hipStream_t s);
+
+}  // namespace mpsim

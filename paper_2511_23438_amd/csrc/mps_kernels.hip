@@ -1,0 +1,151 @@
+// Element-wise and reduction kernels of the block-MPS update and measurement.
+#include "mps_kernels.h"
+
+#include <algorithm>
+#include <cfloat>
+
+namespace mpsim {
+
+// Single-site gate on the physical leg (intra-block gates and the transverse
+// layer are site-local: the bond dimensions do not change).
+__global__ __launch_bounds__(256) void k_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U) {
+  __shared__ cplx Us[256];
+  for (int i = threadIdx.x; i < d * d; i += blockDim.x) Us[i] = U[i];
+  __syncthreads();
+  const long pairs = (long)b0 * b1;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < pairs;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long a = idx / b1, c = idx % b1;
+    cplx v[16];
+    for (int t = 0; t < d; ++t) v[t] = site[(a * d + t) * b1 + c];
+    for (int s = 0; s < d; ++s) {
+      cplx acc = make_double2(0.0, 0.0);
+      for (int t = 0; t < d; ++t) acc = cadd(acc, cmul(Us[s * d + t], v[t]));
+      site[(a * d + s) * b1 + c] = acc;
+    }
+  }
+}
+
+void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream_t s) {
+  long pairs = (long)b0 * b1;
+  int blocks = (int)std::min<long>((pairs + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_apply_u1, dim3(std::max(blocks, 1)), dim3(256), 0, s, site, b0, d, b1, U);
+}
+
+#define NORM_BLOCKS 512
+__global__ __launch_bounds__(256) void k_norm2_part(const cplx* x, long len, double* partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x)
+    acc += cabs2(x[i]);
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_norm2_final(const double* partial, int np, double* dst) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) *dst = acc;
+}
+
+void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2_part, dim3(NORM_BLOCKS), dim3(256), 0, s, x, len, partial);
+  hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(256), 0, s, (const double*)partial, NORM_BLOCKS, dst);
+}
+
+__global__ void k_trunc_finalize(double* sc, double* flog, long idx, const double* lam, int q, int extra,
+                                 int* flag) {
+  const double nM = sc[2], nC = sc[3];
+  const double f = nC / nM;
+  double gap = INFINITY;
+  if (extra) {
+    const double lmax = fmax(lam[q], 0.0), lq = fmax(lam[1], 0.0), lq1 = fmax(lam[0], 0.0);
+    if (lmax > 0.0) gap = (sqrt(lq) - sqrt(lq1)) / sqrt(lmax);
+  }
+  if (!(f > 0.0) || !isfinite(f) || !(nC > 0.0)) *flag = 1;
+  sc[0] += log(f);
+  sc[1] = fmin(sc[1], gap);
+  sc[4] = 1.0 / sqrt(nC);
+  flog[2 * idx] = f;
+  flog[2 * idx + 1] = gap;
+}
+
+void launch_trunc_finalize(double* sc, double* flog, long idx, const double* lam, int q, int extra,
+                           int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_trunc_finalize, dim3(1), dim3(1), 0, s, sc, flog, idx, lam, q, extra, flag);
+}
+
+__global__ void k_scale_by(cplx* x, long len, const double* sc) {
+  const double f = sc[4];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x)
+    x[i] = cscale(x[i], f);
+}
+
+void launch_scale_by(cplx* x, long len, const double* sc, hipStream_t s) {
+  int blocks = (int)std::min<long>((len + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_scale_by, dim3(std::max(blocks, 1)), dim3(256), 0, s, x, len, sc);
+}
+
+// 32x32 LDS tiles for coalesced reads and writes.
+__global__ __launch_bounds__(256) void k_conj_transpose(const cplx* src, int rows, int cols, long lds,
+                                                        cplx* dst, long ldd) {
+  __shared__ cplx tile[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = src[(long)r * lds + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) dst[(long)c * ldd + r] = cconj(tile[tx][k]);
+  }
+}
+
+void launch_conj_transpose(const cplx* src, int rows, int cols, long lds, cplx* dst, long ldd,
+                           hipStream_t s) {
+  dim3 grid(ceil_div(cols, 32), ceil_div(rows, 32));
+  hipLaunchKernelGGL(k_conj_transpose, grid, dim3(256), 0, s, src, rows, cols, lds, dst, ldd);
+}
+
+__global__ void k_meas_combine(cplx* X, int b, int d, int b2, const double* zsum) {
+  const long blk = (long)b * d * b2;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < blk; i += (long)gridDim.x * blockDim.x) {
+    const int sidx = (int)((i / b2) % d);
+    const double z = zsum[sidx];
+    const cplx x0 = X[i], x1 = X[blk + i], x2 = X[2 * blk + i];
+    X[2 * blk + i] = cadd(cadd(x2, cscale(x1, 2.0 * z)), cscale(x0, z * z));
+    X[blk + i] = cadd(x1, cscale(x0, z));
+  }
+}
+
+void launch_meas_combine(cplx* X, int b, int d, int b2, const double* zsum, hipStream_t s) {
+  long blk = (long)b * d * b2;
+  int blocks = (int)std::min<long>((blk + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_meas_combine, dim3(std::max(blocks, 1)), dim3(256), 0, s, X, b, d, b2, zsum);
+}
+
+__global__ void k_env_init(cplx* E) {
+  E[0] = make_double2(1.0, 0.0);
+  E[1] = make_double2(0.0, 0.0);
+  E[2] = make_double2(0.0, 0.0);
+}
+
+void launch_env_init(cplx* E, hipStream_t s) {
+  hipLaunchKernelGGL(k_env_init, dim3(1), dim3(1), 0, s, E);
+}
+
+__global__ void k_fill(cplx* x, long len, cplx v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+void launch_fill(cplx* x, long len, cplx v, hipStream_t s) {
+  int blocks = (int)std::min<long>((len + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill, dim3(std::max(blocks, 1)), dim3(256), 0, s, x, len, v);
+}
+
+}  // namespace mpsim

@@ -1,0 +1,822 @@
+// C-ABI of the block-MPS Trotter evolution (see include/mpsim.h).
+//
+// One handle = one MPS instance resident in HBM. Bond dimensions, block
+// order and the orthogonality centre are tracked on the host (they follow
+// from the schedule and chi alone), so a Trotter step is a pure sequence of
+// asynchronous launches on the handle's stream; device-side failures are
+// raised through a flag checked at the synchronising calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpsim.h"
+#include "common.h"
+#include "gemm.h"
+#include "linalg.h"
+#include "mps_kernels.h"
+#include "planner.h"
+
+using namespace mpsim;
+
+static thread_local std::string g_tl_error;
+
+struct mps_sim {
+  mps_config cfg{};
+  Plan plan;
+  hipStream_t stream = nullptr;
+  mps_allocator alloc{};
+  bool has_alloc = false;
+  std::vector<void*> allocations;
+
+  std::vector<cplx*> site;
+  std::vector<int> bond, pos;
+  int centre = 0;
+  int steps = 0;
+  uint64_t nupdates = 0;
+
+  long tmp_elems = 0, theta_elems = 0, gram_elems = 0, env_elems = 0, envx_elems = 0;
+  cplx* theta = nullptr;
+  cplx* gram = nullptr;
+  cplx* tmpA = nullptr;
+  cplx* tmpB = nullptr;
+  cplx* tmpC = nullptr;
+  cplx* env[2] = {nullptr, nullptr};
+  cplx* envx = nullptr;
+  double* dscal = nullptr;   // [0] logF [1] min gap [2] |M|^2 [3] |C|^2 [4] 1/|C|
+  double* dpartial = nullptr;
+  double* flog = nullptr;
+  long log_cap = 0, nlog = 0;
+  LinalgWork lw;
+
+  cplx* d_pairs = nullptr;
+  std::vector<long> pair_off;
+  cplx* d_gates = nullptr;
+  std::vector<long> gate_off[3];
+  double* d_zsum = nullptr;
+  std::vector<long> zsum_off;
+
+  std::string err;
+  int failed = 0;
+};
+
+// ---------------------------------------------------------------------------
+namespace {
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) throw HipError{_e, #expr};  \
+  } while (0)
+
+struct NoMem {};
+
+void* dev_alloc(mps_sim* h, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (h->has_alloc) {
+    p = h->alloc.alloc(h->alloc.ctx, bytes, (void*)h->stream);
+    if (!p) throw NoMem{};
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw NoMem{};
+    }
+  }
+  h->allocations.push_back(p);
+  return p;
+}
+
+template <typename T>
+T* dalloc(mps_sim* h, long count) {
+  return (T*)dev_alloc(h, sizeof(T) * (size_t)std::max<long>(count, 1));
+}
+
+struct Sizes {
+  long site_max = 0, sites_total = 0, theta = 0, gram = 0, nmax = 1, qmax = 1, mmax = 1,
+       colmax = 1, tmp = 0, env = 0, envx = 0;
+};
+
+Sizes plan_sizes(const Plan& p) {
+  Sizes z;
+  const long D = p.dmax;
+  for (int s = 0; s < p.N; ++s) {
+    long e = (long)p.cap[s] * D * p.cap[s + 1];
+    z.site_max = std::max(z.site_max, e);
+    z.sites_total += e;
+    z.mmax = std::max(z.mmax, std::max((long)p.cap[s] * D, D * p.cap[s + 1]));
+    z.colmax = std::max(z.colmax, (long)std::max(p.cap[s], p.cap[s + 1]));
+  }
+  for (int i = 0; i + 1 < p.N; ++i) {
+    long mo = (long)p.cap[i] * D, no = D * p.cap[i + 2];
+    z.theta = std::max(z.theta, mo * no);
+    long kg = std::min(mo, no);
+    z.gram = std::max(z.gram, kg * kg);
+    z.nmax = std::max(z.nmax, kg);
+    z.qmax = std::max(z.qmax, std::min<long>(p.chi, kg));
+  }
+  // bond spectrum Gram (cap x cap) also fits: cap <= kg bound
+  z.mmax = std::max(z.mmax, z.nmax);
+  z.colmax = std::max(z.colmax, z.qmax);
+  z.tmp = std::max(z.site_max, z.nmax * z.qmax);
+  long cmax = 1;
+  for (int s = 0; s <= p.N; ++s) cmax = std::max(cmax, (long)p.cap[s]);
+  z.env = 3 * cmax * cmax;
+  z.envx = 3 * z.site_max;
+  return z;
+}
+
+struct LwSizes {
+  long W, tpart, P, dpart, npart, iwork, T, V, W12, gpart;
+};
+
+LwSizes lw_sizes(const Sizes& z) {
+  LwSizes l;
+  l.W = z.nmax * TRD_NB;
+  long nparts = (long)ceil_div(z.mmax, 256) * 4;
+  l.tpart = std::max(nparts * (2 * TRD_NB + 1), nparts * QR_NB);
+  long nt = ceil_div(z.nmax, 64);
+  l.P = nt * nt * 64;
+  l.dpart = nparts;
+  l.npart = nparts;
+  l.iwork = 6 * z.nmax * z.qmax;
+  l.T = ((long)z.colmax / QR_NB + 2) * 4096;
+  l.V = std::max(z.nmax, z.mmax) * 64;
+  l.W12 = 64 * z.colmax;
+  l.gpart = 4L << 20;
+  return l;
+}
+
+size_t footprint(const Plan& p) {
+  Sizes z = plan_sizes(p);
+  LwSizes l = lw_sizes(z);
+  size_t c = sizeof(cplx), d = sizeof(double);
+  size_t total = 0;
+  total += (size_t)z.sites_total * c;
+  total += (size_t)(z.theta + z.gram + 3 * z.tmp + 2 * z.env + z.envx) * c;
+  total += (size_t)(l.W + l.tpart + l.P + l.dpart + l.T + 4096 + 2 * l.W12 + l.V + l.gpart) * c;
+  total += (size_t)(l.npart + l.iwork + 4 * z.nmax + z.qmax + 2 + 16 + 2 * 4096) * d;
+  total += (size_t)(z.nmax + z.colmax) * c;
+  return total;
+}
+
+mps_status fail(mps_sim* h, mps_status st, const std::string& msg) {
+  if (h) {
+    h->err = msg;
+    if (st == MPS_E_DEVICE || st == MPS_E_NUMERIC) h->failed = 1;
+  } else {
+    g_tl_error = msg;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// building blocks
+
+void norm2(mps_sim* h, const cplx* x, long len, int slot) {
+  launch_norm2(x, len, h->dpartial, h->dscal + slot, h->stream);
+}
+
+void ensure_log(mps_sim* h, long need) {
+  if (need <= h->log_cap) return;
+  long ncap = std::max(need, 2 * h->log_cap);
+  double* nl = dalloc<double>(h, 2 * ncap);
+  if (h->nlog > 0)
+    HIPCHK(hipMemcpyAsync(nl, h->flog, sizeof(double) * 2 * h->nlog, hipMemcpyDeviceToDevice, h->stream));
+  h->flog = nl;  // old buffer stays owned by the handle until mps_free
+  h->log_cap = ncap;
+}
+
+// Move the orthogonality centre one site right: QR of site c.
+void move_right(mps_sim* h) {
+  const int c = h->centre;
+  const Plan& p = h->plan;
+  const int b0 = h->bond[c], d = p.dim(h->pos[c]), b1 = h->bond[c + 1];
+  const int m = b0 * d, k = b1, kmin = std::min(m, k);
+  const int d2 = p.dim(h->pos[c + 1]), b2 = h->bond[c + 2];
+  hipStream_t s = h->stream;
+  HIPCHK(hipMemcpyAsync(h->tmpA, h->site[c], sizeof(cplx) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
+  qr_factor(m, k, h->tmpA, k, 1, h->lw, s);
+  qr_form_q(m, k, h->tmpA, k, 1, h->lw, h->site[c], kmin, s);
+  qr_get_r(m, k, h->tmpA, k, 1, h->tmpB, k, s);
+  // site c+1 <- R * site c+1  (kmin x k) (k x d2*b2)
+  ZGemm g = zgemm_args(kmin, d2 * b2, k, zop(h->tmpB, k, 0), zop(h->site[c + 1], (long)d2 * b2, 0),
+                       h->tmpC, (long)d2 * b2, 0, make_double2(1, 0), make_double2(0, 0));
+  zgemm(g, h->lw.gpart, h->lw.gpart_elems, s);
+  HIPCHK(hipMemcpyAsync(h->site[c + 1], h->tmpC, sizeof(cplx) * (size_t)kmin * d2 * b2,
+                        hipMemcpyDeviceToDevice, s));
+  h->bond[c + 1] = kmin;
+  h->centre = c + 1;
+}
+
+// Move the centre one site left: LQ of site c (QR of its conjugate transpose).
+void move_left(mps_sim* h) {
+  const int c = h->centre;
+  const Plan& p = h->plan;
+  const int b0 = h->bond[c], d = p.dim(h->pos[c]), b1 = h->bond[c + 1];
+  const int rows = b0, cols = d * b1;  // site as b0 x (d*b1)
+  const int m = cols, k = rows, kmin = std::min(m, k);
+  const int bp = h->bond[c - 1], dp = p.dim(h->pos[c - 1]);
+  hipStream_t s = h->stream;
+  // Y = site^H (m x k row-major)
+  launch_conj_transpose(h->site[c], rows, cols, cols, h->tmpA, k, s);
+  qr_factor(m, k, h->tmpA, k, 1, h->lw, s);
+  qr_form_q(m, k, h->tmpA, k, 1, h->lw, h->tmpB, kmin, s);  // Q: m x kmin
+  // new site c = Q^H (kmin x m)
+  launch_conj_transpose(h->tmpB, m, kmin, kmin, h->site[c], m, s);
+  qr_get_r(m, k, h->tmpA, k, 1, h->tmpB, k, s);  // R: kmin x k
+  // site c-1 <- site c-1 * R^H : (bp*dp x k) (k x kmin)
+  ZGemm g = zgemm_args(bp * dp, kmin, k, zop(h->site[c - 1], k, 0), zop(h->tmpB, k, 1, 1), h->tmpC,
+                       kmin, 0, make_double2(1, 0), make_double2(0, 0));
+  zgemm(g, h->lw.gpart, h->lw.gpart_elems, s);
+  HIPCHK(hipMemcpyAsync(h->site[c - 1], h->tmpC, sizeof(cplx) * (size_t)bp * dp * kmin,
+                        hipMemcpyDeviceToDevice, s));
+  h->bond[c] = kmin;
+  h->centre = c - 1;
+}
+
+void move_centre(mps_sim* h, int target) {
+  while (h->centre < target) move_right(h);
+  while (h->centre > target) move_left(h);
+}
+
+// Two-site update on (i, i+1): theta = A_i A_{i+1} with the block-pair phase
+// (and SWAP) fused into the GEMM epilogue, then truncation to
+// q = min(chi, rows, cols) through the top-q eigenspace of the Gram matrix on
+// the smaller side, fidelity bookkeeping and renormalisation.
+void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
+  const Plan& p = h->plan;
+  if (h->centre < i) move_centre(h, i);
+  else if (h->centre > i + 1) move_centre(h, i + 1);
+  hipStream_t s = h->stream;
+  const int ba = h->pos[i], bb = h->pos[i + 1];
+  const int b0 = h->bond[i], d1 = p.dim(ba), b1 = h->bond[i + 1], d2 = p.dim(bb), b2 = h->bond[i + 2];
+  const long m = (long)b0 * d1, n = (long)d2 * b2;
+  const long mo = swap ? (long)b0 * d2 : m, no = swap ? (long)d1 * b2 : n;
+  const int q = (int)std::min<long>(p.chi, std::min(mo, no));
+
+  // theta
+  ZGemm g = zgemm_args((int)m, (int)n, b1, zop(h->site[i], b1, 0), zop(h->site[i + 1], n, 0), h->theta,
+                       n, 0, make_double2(1, 0), make_double2(0, 0));
+  g.epi = EPI_THETA;
+  g.d1 = d1; g.d2 = d2; g.b2 = b2; g.swap = swap;
+  g.phase = nullptr;
+  if (gate) {
+    int pi = p.coupled(ba, bb);
+    if (pi >= 0) {
+      g.phase = h->d_pairs + h->pair_off[pi];
+      g.phase_trans = (ba > bb) ? 1 : 0;
+    }
+  }
+  zgemm(g, nullptr, 0, s);
+  norm2(h, h->theta, mo * no, 2);
+
+  bool left;
+  if (mo != no) left = mo < no;
+  else left = !(next_site >= 0 && next_site < i);
+  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->nupdates;
+  const int extra = (q < (left ? mo : no)) ? 1 : 0;
+  const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
+  if (left) {
+    const int kg = (int)mo;
+    // G = M M^H stored column-major (lower triangle)
+    ZGemm gg = zgemm_args(kg, kg, (int)no, zop(h->theta, no, 0), zop(h->theta, no, 1, 1), h->gram, kg, 1,
+                          one, zero);
+    gg.lower_only = 1;
+    zgemm(gg, nullptr, 0, s);
+    heev_top(kg, h->gram, kg, q, h->site[i], q, h->tmpA, h->lw, seed, s);
+    // C = U^H M -> site i+1 (q x no)
+    ZGemm gc = zgemm_args(q, (int)no, kg, zop(h->site[i], q, 1, 1), zop(h->theta, no, 0), h->site[i + 1],
+                          no, 0, one, zero);
+    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s);
+    norm2(h, h->site[i + 1], (long)q * no, 3);
+    ensure_log(h, h->nlog + 1);
+    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_scale_by(h->site[i + 1], (long)q * no, h->dscal, s);
+    h->centre = i + 1;
+  } else {
+    const int kg = (int)no;
+    // G = M^H M stored column-major (lower triangle)
+    ZGemm gg = zgemm_args(kg, kg, (int)mo, zop(h->theta, no, 1, 1), zop(h->theta, no, 0), h->gram, kg, 1,
+                          one, zero);
+    gg.lower_only = 1;
+    zgemm(gg, nullptr, 0, s);
+    heev_top(kg, h->gram, kg, q, h->tmpB, q, h->tmpA, h->lw, seed, s);
+    launch_conj_transpose(h->tmpB, kg, q, q, h->site[i + 1], kg, s);
+    // C = M V -> site i (mo x q)
+    ZGemm gc = zgemm_args((int)mo, q, kg, zop(h->theta, no, 0), zop(h->tmpB, q, 0), h->site[i], q, 0, one,
+                          zero);
+    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s);
+    norm2(h, h->site[i], mo * q, 3);
+    ensure_log(h, h->nlog + 1);
+    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_scale_by(h->site[i], mo * q, h->dscal, s);
+    h->centre = i;
+  }
+  h->nlog += 1;
+  h->nupdates += 1;
+  h->bond[i + 1] = q;
+  if (swap) std::swap(h->pos[i], h->pos[i + 1]);
+}
+
+void single_site(mps_sim* h, int site, int variant) {
+  const Plan& p = h->plan;
+  const int b = h->pos[site];
+  launch_apply_u1(h->site[site], h->bond[site], p.dim(b), h->bond[site + 1],
+                  h->d_gates + h->gate_off[variant][b], h->stream);
+}
+
+void run_step(mps_sim* h) {
+  std::vector<Op> ops;
+  std::vector<int> pos = h->pos;
+  h->plan.step_ops(pos, ops);
+  for (size_t k = 0; k < ops.size(); ++k) {
+    const Op& o = ops[k];
+    if (o.kind == 1) {
+      int next = -1;
+      for (size_t k2 = k + 1; k2 < ops.size(); ++k2)
+        if (ops[k2].kind == 1) { next = ops[k2].site; break; }
+      two_site(h, o.site, o.swap, o.gate, next);
+    } else {
+      single_site(h, o.site, o.variant);
+    }
+  }
+  h->steps += 1;
+}
+
+mps_status check_device(mps_sim* h) {
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(h, MPS_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+  int flag = 0;
+  e = hipMemcpy(&flag, h->lw.flag, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(h, MPS_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+  if (flag) return fail(h, MPS_E_NUMERIC, "non-finite or zero norm in a truncation");
+  return MPS_OK;
+}
+
+// Measurement sweep: three left environments for 1, Z_tot and Z_tot^2.
+void measure_sweep(mps_sim* h, double out[3]) {
+  const Plan& p = h->plan;
+  hipStream_t s = h->stream;
+  launch_env_init(h->env[0], s);
+  int cur = 0;
+  const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
+  for (int st = 0; st < p.N; ++st) {
+    const int b = h->bond[st], blk = h->pos[st], d = p.dim(blk), b2 = h->bond[st + 1];
+    const long xs = (long)b * d * b2;
+    // X_k = E_k A
+    ZGemm g1 = zgemm_args(b, d * b2, b, zop(h->env[cur], b, 0), zop(h->site[st], (long)d * b2, 0), h->envx,
+                          (long)d * b2, 0, one, zero);
+    g1.batch = 3;
+    g1.A.stride = (long)b * b;
+    g1.B.stride = 0;
+    g1.strideC = xs;
+    zgemm(g1, nullptr, 0, s);
+    launch_meas_combine(h->envx, b, d, b2, h->d_zsum + h->zsum_off[blk], s);
+    // E'_k = A^H Y_k
+    ZGemm g2 = zgemm_args(b2, b2, b * d, zop(h->site[st], b2, 1, 1), zop(h->envx, b2, 0), h->env[1 - cur], b2,
+                          0, one, zero);
+    g2.batch = 3;
+    g2.A.stride = 0;
+    g2.B.stride = xs;
+    g2.strideC = (long)b2 * b2;
+    zgemm(g2, nullptr, 0, s);
+    cur = 1 - cur;
+  }
+  cplx host[3];
+  HIPCHK(hipMemcpyAsync(host, h->env[cur], sizeof(cplx) * 3, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < 3; ++k) out[k] = host[k].x;
+}
+
+void upload_product_state(mps_sim* h) {
+  const Plan& p = h->plan;
+  const double c = std::cos(p.theta0 / 2), sn = std::sin(p.theta0 / 2);
+  for (int st = 0; st < p.N; ++st) {
+    const int blk = h->pos[st], w = p.block_width[blk], d = p.dim(blk);
+    std::vector<cplx> v(d);
+    for (int idx = 0; idx < d; ++idx) {
+      double amp = 1.0;
+      for (int j = 0; j < w; ++j) amp *= (((idx >> (w - 1 - j)) & 1) == 0) ? c : sn;
+      v[idx] = make_double2(amp, 0.0);
+    }
+    HIPCHK(hipMemcpy(h->site[st], v.data(), sizeof(cplx) * d, hipMemcpyHostToDevice));
+  }
+}
+
+void reset_bookkeeping(mps_sim* h) {
+  double sc[5] = {0.0, INFINITY, 0.0, 0.0, 0.0};
+  HIPCHK(hipMemcpy(h->dscal, sc, sizeof(sc), hipMemcpyHostToDevice));
+  int zero = 0;
+  HIPCHK(hipMemcpy(h->lw.flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+  h->nlog = 0;
+  h->steps = 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+mps_status mps_footprint_bytes(const mps_config* cfg, size_t* bytes) {
+  const char* msg;
+  mps_status st = validate(cfg, &msg);
+  if (st != MPS_OK) return fail(nullptr, st, msg);
+  if (!bytes) return fail(nullptr, MPS_E_INVAL, "bytes is NULL");
+  Plan p;
+  build_plan(cfg, p);
+  *bytes = footprint(p);
+  return MPS_OK;
+}
+
+mps_status mps_schedule_dump(const mps_config* cfg, int32_t nsteps, int32_t* ops, int32_t cap,
+                             int32_t* len) {
+  const char* msg;
+  mps_status st = validate(cfg, &msg);
+  if (st != MPS_OK) return fail(nullptr, st, msg);
+  if (!len || nsteps < 0 || (cap > 0 && !ops)) return fail(nullptr, MPS_E_INVAL, "bad arguments");
+  Plan p;
+  build_plan(cfg, p);
+  std::vector<int> pos = p.snake();
+  std::vector<Op> all;
+  for (int k = 0; k < nsteps; ++k) p.step_ops(pos, all);
+  const long need = 6L * (long)all.size();
+  *len = (int32_t)need;
+  if (need > cap) return fail(nullptr, MPS_E_INVAL, "ops buffer too small");
+  for (size_t k = 0; k < all.size(); ++k) {
+    const Op& o = all[k];
+    int32_t* r = ops + 6 * k;
+    if (o.kind == 1) {
+      r[0] = 1; r[1] = o.site; r[2] = o.swap; r[3] = o.gate; r[4] = o.block_a; r[5] = o.block_b;
+    } else {
+      r[0] = 2; r[1] = o.site; r[2] = o.variant; r[3] = o.block_a; r[4] = 0; r[5] = 0;
+    }
+  }
+  return MPS_OK;
+}
+
+mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, void* hip_stream,
+                            mps_handle* out) {
+  if (!out) return fail(nullptr, MPS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  const char* msg;
+  mps_status st = validate(cfg, &msg);
+  if (st != MPS_OK) return fail(nullptr, st, msg);
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(nullptr, MPS_E_INVAL, "allocator incomplete");
+  mps_sim* h = new mps_sim();
+  h->cfg = *cfg;
+  h->stream = (hipStream_t)hip_stream;
+  if (alloc) {
+    h->alloc = *alloc;
+    h->has_alloc = true;
+  }
+  try {
+    build_plan(cfg, h->plan);
+    const Plan& p = h->plan;
+    Sizes z = plan_sizes(p);
+    LwSizes l = lw_sizes(z);
+    h->site.resize(p.N);
+    for (int s = 0; s < p.N; ++s) h->site[s] = dalloc<cplx>(h, (long)p.cap[s] * p.dmax * p.cap[s + 1]);
+    h->theta = dalloc<cplx>(h, z.theta);
+    h->gram = dalloc<cplx>(h, z.gram);
+    h->tmpA = dalloc<cplx>(h, z.tmp);
+    h->tmpB = dalloc<cplx>(h, z.tmp);
+    h->tmpC = dalloc<cplx>(h, z.tmp);
+    h->env[0] = dalloc<cplx>(h, z.env);
+    h->env[1] = dalloc<cplx>(h, z.env);
+    h->envx = dalloc<cplx>(h, z.envx);
+    h->dscal = dalloc<double>(h, 16);
+    h->dpartial = dalloc<double>(h, 4096);
+    LinalgWork& w = h->lw;
+    w.nmax = z.nmax; w.qmax = z.qmax; w.mmax = z.mmax;
+    w.W = dalloc<cplx>(h, l.W);
+    w.tpart = dalloc<cplx>(h, l.tpart);
+    w.tpart_elems = l.tpart;
+    w.P = dalloc<cplx>(h, l.P);
+    w.P_elems = l.P;
+    w.dpart = dalloc<cplx>(h, l.dpart);
+    w.npart = dalloc<double>(h, l.npart);
+    w.d = dalloc<double>(h, z.nmax);
+    w.e = dalloc<double>(h, z.nmax);
+    w.e2 = dalloc<double>(h, z.nmax);
+    w.tau = dalloc<cplx>(h, z.nmax);
+    w.qtau = dalloc<cplx>(h, z.colmax);
+    w.scal = dalloc<double>(h, 16);
+    w.lam = dalloc<double>(h, z.qmax + 2);
+    w.iwork = dalloc<double>(h, l.iwork);
+    w.T = dalloc<cplx>(h, l.T);
+    w.T_elems = l.T;
+    w.S = dalloc<cplx>(h, 4096);
+    w.wmax = z.colmax;
+    w.W1 = dalloc<cplx>(h, l.W12);
+    w.W2 = dalloc<cplx>(h, l.W12);
+    w.vmax = std::max(z.nmax, z.mmax);
+    w.V = dalloc<cplx>(h, l.V);
+    w.gpart = dalloc<cplx>(h, l.gpart);
+    w.gpart_elems = l.gpart;
+    w.flag = dalloc<int>(h, 4);
+    // gate tables
+    long off = 0;
+    for (auto& t : p.pair_phase) { h->pair_off.push_back(off); off += (long)t.size(); }
+    h->d_pairs = dalloc<cplx>(h, off);
+    {
+      std::vector<cplx> hp(std::max<long>(off, 1));
+      long o2 = 0;
+      for (auto& t : p.pair_phase)
+        for (auto& z2 : t) hp[o2++] = make_double2(z2.real(), z2.imag());
+      if (off) HIPCHK(hipMemcpy(h->d_pairs, hp.data(), sizeof(cplx) * off, hipMemcpyHostToDevice));
+    }
+    long goff = 0;
+    std::vector<cplx> hg;
+    for (int v = 0; v < 3; ++v)
+      for (int b = 0; b < p.nblocks(); ++b) {
+        h->gate_off[v].push_back(goff);
+        for (auto& z2 : p.site_gate[v][b]) hg.push_back(make_double2(z2.real(), z2.imag()));
+        goff += (long)p.site_gate[v][b].size();
+      }
+    h->d_gates = dalloc<cplx>(h, goff);
+    HIPCHK(hipMemcpy(h->d_gates, hg.data(), sizeof(cplx) * goff, hipMemcpyHostToDevice));
+    std::vector<double> hz;
+    for (int b = 0; b < p.nblocks(); ++b) {
+      h->zsum_off.push_back((long)hz.size());
+      for (double zz : p.zsum[b]) hz.push_back(zz);
+    }
+    h->d_zsum = dalloc<double>(h, (long)hz.size());
+    HIPCHK(hipMemcpy(h->d_zsum, hz.data(), sizeof(double) * hz.size(), hipMemcpyHostToDevice));
+    // state
+    h->pos = p.snake();
+    h->bond.assign(p.N + 1, 1);
+    h->centre = 0;
+    upload_product_state(h);
+    h->log_cap = 0;
+    ensure_log(h, 64L * (11 * p.R + 4));
+    reset_bookkeeping(h);
+    HIPCHK(hipDeviceSynchronize());
+  } catch (NoMem&) {
+    mps_free(h);
+    return fail(nullptr, MPS_E_NOMEM, "device allocation failed");
+  } catch (HipError& e) {
+    std::string m = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+    mps_free(h);
+    return fail(nullptr, MPS_E_DEVICE, m);
+  }
+  *out = h;
+  return MPS_OK;
+}
+
+#define GUARD(h)                                                     \
+  if (!(h)) return fail(nullptr, MPS_E_INVAL, "handle is NULL");     \
+  if ((h)->failed) return fail((h), MPS_E_STATE, "handle has failed")
+
+#define TRYDEV(h, ...)                                                                       \
+  try {                                                                                      \
+    __VA_ARGS__;                                                                             \
+  } catch (HipError & e) {                                                                   \
+    return fail((h), MPS_E_DEVICE, std::string("HIP error in ") + e.what + ": " +            \
+                                       hipGetErrorString(e.e));                              \
+  } catch (NoMem&) {                                                                         \
+    return fail((h), MPS_E_DEVICE, "device allocation failed");                              \
+  }
+
+mps_status mps_apply_trotter_step(mps_handle h, int32_t nsteps) {
+  GUARD(h);
+  if (nsteps < 0) return fail(h, MPS_E_INVAL, "nsteps < 0");
+  TRYDEV(h, for (int k = 0; k < nsteps; ++k) run_step(h); HIPCHK(hipGetLastError()));
+  return MPS_OK;
+}
+
+mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t nsteps) {
+  if (!hs || count < 0 || nsteps < 0) return fail(nullptr, MPS_E_INVAL, "bad arguments");
+  for (int k = 0; k < count; ++k) {
+    if (!hs[k]) return fail(nullptr, MPS_E_INVAL, "NULL handle in batch");
+    if (hs[k]->failed) return fail(hs[k], MPS_E_STATE, "handle has failed");
+  }
+  for (int st = 0; st < nsteps; ++st)
+    for (int k = 0; k < count; ++k) {
+      mps_sim* h = hs[k];
+      TRYDEV(h, run_step(h); HIPCHK(hipGetLastError()));
+    }
+  return MPS_OK;
+}
+
+mps_status mps_sync(mps_handle h) {
+  GUARD(h);
+  return check_device(h);
+}
+
+mps_status mps_measure(mps_handle h, double gamma, mps_obs* out) {
+  GUARD(h);
+  if (!out) return fail(h, MPS_E_INVAL, "out is NULL");
+  double e[3];
+  double sc[2];
+  TRYDEV(h, measure_sweep(h, e);
+         HIPCHK(hipMemcpy(sc, h->dscal, sizeof(sc), hipMemcpyDeviceToHost)));
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  const double n = h->plan.n;
+  mps_obs o{};
+  o.step = h->steps;
+  o.norm = e[0];
+  o.z = e[1] / (n * e[0]);
+  o.z2 = e[2] / (n * n * e[0]);
+  if (!std::isfinite(o.z) || !std::isfinite(o.z2)) return fail(h, MPS_E_NUMERIC, "non-finite observable");
+  o.log_fidelity = sc[0];
+  o.fidelity = std::exp(sc[0]);
+  o.min_gap = sc[1];
+  o.z_rescaled = o.fidelity * o.z;
+  o.gamma = gamma;
+  o.z2_rescaled = gamma >= 0 ? o.z2 * std::pow(o.fidelity, gamma) : NAN;
+  *out = o;
+  return MPS_OK;
+}
+
+mps_status mps_fidelity(mps_handle h, double* fidelity, double* log_fidelity) {
+  GUARD(h);
+  if (!fidelity || !log_fidelity) return fail(h, MPS_E_INVAL, "NULL output");
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  double sc = 0;
+  if (hipMemcpy(&sc, h->dscal, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, MPS_E_DEVICE, "copy failed");
+  *log_fidelity = sc;
+  *fidelity = std::exp(sc);
+  return MPS_OK;
+}
+
+void mps_free(mps_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->allocations) {
+    if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, (void*)h->stream);
+    else (void)hipFree(p);
+  }
+  delete h;
+}
+
+mps_status mps_bond_dims(mps_handle h, int32_t* dims, int32_t cap, int32_t* len) {
+  GUARD(h);
+  if (!len) return fail(h, MPS_E_INVAL, "len is NULL");
+  *len = (int32_t)h->bond.size();
+  if (cap < *len || !dims) return fail(h, MPS_E_INVAL, "buffer too small");
+  for (size_t k = 0; k < h->bond.size(); ++k) dims[k] = h->bond[k];
+  return MPS_OK;
+}
+
+mps_status mps_site_blocks(mps_handle h, int32_t* blocks, int32_t cap, int32_t* len) {
+  GUARD(h);
+  if (!len) return fail(h, MPS_E_INVAL, "len is NULL");
+  *len = (int32_t)h->pos.size();
+  if (cap < *len || !blocks) return fail(h, MPS_E_INVAL, "buffer too small");
+  for (size_t k = 0; k < h->pos.size(); ++k) blocks[k] = h->pos[k];
+  return MPS_OK;
+}
+
+mps_status mps_get_site(mps_handle h, int32_t p, double* re_im, int64_t cap, int32_t* dims) {
+  GUARD(h);
+  if (p < 0 || p >= h->plan.N || !dims) return fail(h, MPS_E_INVAL, "bad site");
+  const int b0 = h->bond[p], d = h->plan.dim(h->pos[p]), b1 = h->bond[p + 1];
+  dims[0] = b0; dims[1] = d; dims[2] = b1;
+  const long len = (long)b0 * d * b1;
+  if (cap < len || !re_im) return fail(h, MPS_E_INVAL, "buffer too small");
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  if (hipMemcpy(re_im, h->site[p], sizeof(cplx) * len, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, MPS_E_DEVICE, "copy failed");
+  return MPS_OK;
+}
+
+mps_status mps_set_state(mps_handle h, const int32_t* bonds, const double* const* sites, int32_t centre) {
+  GUARD(h);
+  const Plan& p = h->plan;
+  if (!bonds || !sites || centre < 0 || centre >= p.N) return fail(h, MPS_E_INVAL, "bad arguments");
+  if (bonds[0] != 1 || bonds[p.N] != 1) return fail(h, MPS_E_INVAL, "end bonds must be 1");
+  for (int b = 0; b <= p.N; ++b)
+    if (bonds[b] < 1 || bonds[b] > p.cap[b]) return fail(h, MPS_E_INVAL, "bond exceeds its cap");
+  for (int s = 0; s < p.N; ++s)
+    if (!sites[s]) return fail(h, MPS_E_INVAL, "NULL site");
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  TRYDEV(h, {
+    std::vector<int> pos = p.snake();
+    for (int s = 0; s < p.N; ++s) {
+      long len = (long)bonds[s] * p.dim(pos[s]) * bonds[s + 1];
+      HIPCHK(hipMemcpy(h->site[s], sites[s], sizeof(cplx) * len, hipMemcpyHostToDevice));
+    }
+    h->pos = pos;
+    h->bond.assign(bonds, bonds + p.N + 1);
+    h->centre = centre;
+    reset_bookkeeping(h);
+  });
+  return MPS_OK;
+}
+
+mps_status mps_apply_two_site(mps_handle h, int32_t site, int32_t swap, int32_t gate) {
+  GUARD(h);
+  if (site < 0 || site + 1 >= h->plan.N) return fail(h, MPS_E_INVAL, "bad site");
+  TRYDEV(h, two_site(h, site, swap ? 1 : 0, gate ? 1 : 0, -1); HIPCHK(hipGetLastError()));
+  return MPS_OK;
+}
+
+mps_status mps_truncation_log(mps_handle h, double* f, double* gap, int32_t cap, int32_t* len) {
+  GUARD(h);
+  if (!len) return fail(h, MPS_E_INVAL, "len is NULL");
+  *len = (int32_t)h->nlog;
+  if (cap < h->nlog || (h->nlog > 0 && (!f || !gap))) return fail(h, MPS_E_INVAL, "buffer too small");
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  std::vector<double> buf(2 * std::max<long>(h->nlog, 1));
+  if (h->nlog > 0 &&
+      hipMemcpy(buf.data(), h->flog, sizeof(double) * 2 * h->nlog, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, MPS_E_DEVICE, "copy failed");
+  for (long k = 0; k < h->nlog; ++k) {
+    f[k] = buf[2 * k];
+    gap[k] = buf[2 * k + 1];
+  }
+  return MPS_OK;
+}
+
+mps_status mps_bond_spectrum(mps_handle h, int32_t bond, double* sv, int32_t cap, int32_t* len) {
+  GUARD(h);
+  const Plan& p = h->plan;
+  if (bond < 1 || bond >= p.N || !len) return fail(h, MPS_E_INVAL, "bad bond");
+  TRYDEV(h, {
+    move_centre(h, bond - 1);
+    const int c = bond - 1;
+    const int b0 = h->bond[c], d = p.dim(h->pos[c]), b1 = h->bond[c + 1];
+    const int m = b0 * d;
+    *len = b1;
+    if (cap < b1 || !sv) return fail(h, MPS_E_INVAL, "buffer too small");
+    // G = A^H A (b1 x b1), eigenvalues = squared Schmidt values
+    ZGemm gg = zgemm_args(b1, b1, m, zop(h->site[c], b1, 1, 1), zop(h->site[c], b1, 0), h->gram, b1, 1,
+                          make_double2(1, 0), make_double2(0, 0));
+    gg.lower_only = 1;
+    zgemm(gg, nullptr, 0, h->stream);
+    hetrd_lower(b1, h->gram, b1, h->lw, h->stream);
+    tridiag_eigvals(b1, 0, b1, h->lw, h->stream);
+    std::vector<double> lam(b1);
+    HIPCHK(hipMemcpyAsync(lam.data(), h->lw.lam, sizeof(double) * b1, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < b1; ++k) sv[k] = std::sqrt(std::max(lam[b1 - 1 - k], 0.0));
+  });
+  return check_device(h);
+}
+
+mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len) {
+  GUARD(h);
+  const Plan& p = h->plan;
+  if (p.n > 20) return fail(h, MPS_E_UNSUPPORTED, "state vector limited to 20 qubits");
+  if (!re_im || len != (1LL << p.n)) return fail(h, MPS_E_INVAL, "len must be 2^n");
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  typedef std::complex<double> zc;
+  // contract on the host (diagnostic only): T has shape (prod d) x b
+  std::vector<zc> T(1, zc(1, 0));
+  long left = 1;
+  for (int s = 0; s < p.N; ++s) {
+    const int b0 = h->bond[s], d = p.dim(h->pos[s]), b1 = h->bond[s + 1];
+    std::vector<zc> A((size_t)b0 * d * b1);
+    if (hipMemcpy(A.data(), h->site[s], sizeof(zc) * A.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(h, MPS_E_DEVICE, "copy failed");
+    std::vector<zc> U((size_t)left * d * b1, zc(0, 0));
+    for (long x = 0; x < left; ++x)
+      for (int a = 0; a < b0; ++a) {
+        const zc t = T[(size_t)x * b0 + a];
+        if (t == zc(0, 0)) continue;
+        for (int sidx = 0; sidx < d; ++sidx)
+          for (int c = 0; c < b1; ++c)
+            U[((size_t)x * d + sidx) * b1 + c] += t * A[((size_t)a * d + sidx) * b1 + c];
+      }
+    T.swap(U);
+    left *= d;
+  }
+  const int n = p.n;
+  for (long x = 0; x < (1L << n); ++x) {
+    long flat = 0;
+    for (int s = 0; s < p.N; ++s) {
+      const auto& qs = p.block_qubits[h->pos[s]];
+      const int w = (int)qs.size();
+      long sidx = 0;
+      for (int j = 0; j < w; ++j) sidx |= ((x >> (n - 1 - qs[j])) & 1L) << (w - 1 - j);
+      flat = flat * (1L << w) + sidx;
+    }
+    re_im[2 * x] = T[flat].real();
+    re_im[2 * x + 1] = T[flat].imag();
+  }
+  return MPS_OK;
+}
+
+const char* mps_last_error(mps_handle h) {
+  if (h) return h->err.c_str();
+  return g_tl_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Host planning: geometry, schedule and gate tables of the block MPS.
+//
+// Model: H = J sum_<ij> Z_i Z_j + h sum_i X_i on an R x C grid with periodic
+// wrap (eq. "hamiltonian"); one Trotter step exp(-i dt H_X) exp(-i dt H_ZZ)
+// (first order) or exp(-i dt H_X/2) exp(-i dt H_ZZ) exp(-i dt H_X/2)
+// (eq. "trotter_step"). Blocks are half rows fused into sites of local
+// dimension 2^width (results section, figure of the 7x8 grouping) on a row
+// snake (supplement, "MPS Ordering").
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <set>
+
+namespace mpsim {
+
+mps_status validate(const mps_config* cfg, const char** msg) {
+  if (!cfg) { *msg = "config is NULL"; return MPS_E_INVAL; }
+  if (cfg->rows < 1 || cfg->cols < 2) { *msg = "need rows >= 1 and cols >= 2"; return MPS_E_INVAL; }
+  if (cfg->cols > 8) { *msg = "cols > 8 (block width > 4, d > 16) unsupported"; return MPS_E_UNSUPPORTED; }
+  if (cfg->rows > 64) { *msg = "rows > 64 unsupported"; return MPS_E_UNSUPPORTED; }
+  if (cfg->chi_max < 1) { *msg = "chi_max must be >= 1"; return MPS_E_INVAL; }
+  if (cfg->chi_max > 4096) { *msg = "chi_max > 4096 unsupported"; return MPS_E_UNSUPPORTED; }
+  if (cfg->precision < 0 || cfg->precision > 2) { *msg = "bad precision"; return MPS_E_INVAL; }
+  if (cfg->trotter_order != 1 && cfg->trotter_order != 2) { *msg = "trotter_order must be 1 or 2"; return MPS_E_INVAL; }
+  if (cfg->schedule != 1) { *msg = "only schedule 1 is supported"; return MPS_E_UNSUPPORTED; }
+  if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
+  if (cfg->reserved != 0) { *msg = "reserved must be 0"; return MPS_E_INVAL; }
+  if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
+      !std::isfinite(cfg->theta0)) { *msg = "non-finite parameter"; return MPS_E_INVAL; }
+  *msg = "";
+  return MPS_OK;
+}
+
+std::vector<int> Plan::snake() const {
+  std::vector<int> pos;
+  for (int r = 0; r < R; ++r) {
+    if (r % 2 == 0) { pos.push_back(2 * r); pos.push_back(2 * r + 1); }
+    else { pos.push_back(2 * r + 1); pos.push_back(2 * r); }
+  }
+  return pos;
+}
+
+void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
+  auto u2 = [&](int site, int swap, int gate) {
+    Op o{};
+    o.kind = 1; o.site = site; o.swap = swap;
+    o.block_a = pos[site]; o.block_b = pos[site + 1];
+    o.gate = (gate && coupled(o.block_a, o.block_b) >= 0) ? 1 : 0;
+    out.push_back(o);
+    if (swap) std::swap(pos[site], pos[site + 1]);
+  };
+  auto u1 = [&](int site, int variant) {
+    Op o{};
+    o.kind = 2; o.site = site; o.variant = variant; o.block_a = pos[site]; o.block_b = -1;
+    out.push_back(o);
+  };
+  if (order == 2)
+    for (int p = 0; p < N; ++p) u1(p, 1);
+  // vertical neighbours facing each other between rows r and r+1
+  for (int r = 0; r + 1 < R; ++r) u2(2 * r + 1, 0, 1);
+  // the two blocks of every row, fused with a SWAP
+  for (int r = 0; r < R; ++r) u2(2 * r, 1, 1);
+  // the other vertical neighbours, now facing each other
+  for (int r = 0; r + 1 < R; ++r) u2(2 * r + 1, 0, 1);
+  // periodic wrap between the last and the first row: route the last-row
+  // block next to its row-0 partner, gate, route back
+  if (periodic && R >= 3) {
+    for (int p0 = 1; p0 >= 0; --p0) {
+      int want = 2 * (R - 1) + (pos[p0] & 1);
+      int t = (int)(std::find(pos.begin(), pos.end(), want) - pos.begin());
+      for (int p = t - 1; p > p0; --p) u2(p, 1, 0);
+      u2(p0, 0, 1);
+      for (int p = p0 + 1; p < t; ++p) u2(p, 1, 0);
+    }
+  }
+  for (int p = 0; p < N; ++p) u1(p, order == 1 ? 0 : 2);
+}
+
+static int zval(int s, int w, int j) { return 1 - 2 * ((s >> (w - 1 - j)) & 1); }
+
+void build_plan(const mps_config* cfg, Plan& p) {
+  p.R = cfg->rows; p.C = cfg->cols; p.n = p.R * p.C; p.N = 2 * p.R;
+  p.chi = cfg->chi_max; p.order = cfg->trotter_order; p.periodic = cfg->periodic;
+  p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
+  p.wL = (p.C + 1) / 2; p.wR = p.C / 2;
+  p.dmax = 1 << p.wL;
+  int nb = p.nblocks();
+  p.block_width.assign(nb, 0);
+  p.block_qubits.assign(nb, {});
+  for (int r = 0; r < p.R; ++r) {
+    p.block_width[2 * r] = p.wL;
+    p.block_width[2 * r + 1] = p.wR;
+    for (int c = 0; c < p.wL; ++c) p.block_qubits[2 * r].push_back(r * p.C + c);
+    for (int c = p.wL; c < p.C; ++c) p.block_qubits[2 * r + 1].push_back(r * p.C + c);
+  }
+  // ZZ bonds: right and down neighbours with wrap, unordered pairs kept once
+  std::set<std::pair<int, int>> seen;
+  p.bonds.clear();
+  for (int r = 0; r < p.R; ++r)
+    for (int c = 0; c < p.C; ++c) {
+      int q = r * p.C + c;
+      int cand[2] = {-1, -1};
+      if (c + 1 < p.C) cand[0] = r * p.C + c + 1;
+      else if (p.periodic) cand[0] = r * p.C;
+      if (r + 1 < p.R) cand[1] = (r + 1) * p.C + c;
+      else if (p.periodic) cand[1] = c;
+      for (int k = 0; k < 2; ++k) {
+        int q2 = cand[k];
+        if (q2 < 0 || q2 == q) continue;
+        std::pair<int, int> key(std::min(q, q2), std::max(q, q2));
+        if (seen.insert(key).second) p.bonds.push_back(key);
+      }
+    }
+  std::vector<int> blk_of(p.n), idx_in(p.n);
+  for (int b = 0; b < nb; ++b)
+    for (size_t j = 0; j < p.block_qubits[b].size(); ++j) {
+      blk_of[p.block_qubits[b][j]] = b;
+      idx_in[p.block_qubits[b][j]] = (int)j;
+    }
+  // block-pair phases D_ab[s_a][s_b] = exp(-i J dt sum_crossing z z')
+  p.pair_index.assign(nb * nb, -1);
+  p.pair_phase.clear();
+  std::vector<std::vector<double>> energy_pair;
+  std::vector<std::vector<double>> energy_intra(nb);
+  for (int b = 0; b < nb; ++b) energy_intra[b].assign(p.dim(b), 0.0);
+  for (auto& bd : p.bonds) {
+    int a = blk_of[bd.first], b = blk_of[bd.second];
+    int ja = idx_in[bd.first], jb = idx_in[bd.second];
+    if (a == b) {
+      int w = p.block_width[a];
+      for (int s = 0; s < p.dim(a); ++s) energy_intra[a][s] += zval(s, w, ja) * zval(s, w, jb);
+      continue;
+    }
+    if (a > b) { std::swap(a, b); std::swap(ja, jb); }
+    int& pi = p.pair_index[a * nb + b];
+    if (pi < 0) {
+      pi = (int)energy_pair.size();
+      energy_pair.push_back(std::vector<double>(p.dim(a) * p.dim(b), 0.0));
+    }
+    int wa = p.block_width[a], wb = p.block_width[b];
+    for (int sa = 0; sa < p.dim(a); ++sa)
+      for (int sb = 0; sb < p.dim(b); ++sb)
+        energy_pair[pi][sa * p.dim(b) + sb] += zval(sa, wa, ja) * zval(sb, wb, jb);
+  }
+  for (auto& e : energy_pair) {
+    std::vector<zc> ph(e.size());
+    for (size_t k = 0; k < e.size(); ++k) ph[k] = std::exp(zc(0.0, -p.J * p.dt * e[k]));
+    p.pair_phase.push_back(ph);
+  }
+  // single-site gates
+  for (int v = 0; v < 3; ++v) p.site_gate[v].assign(nb, {});
+  p.zsum.assign(nb, {});
+  for (int b = 0; b < nb; ++b) {
+    int w = p.block_width[b], d = p.dim(b);
+    auto xlayer = [&](double phi) {
+      // Kronecker power of exp(-i phi X), first qubit most significant
+      std::vector<zc> u(d * d);
+      double c = std::cos(phi), s = std::sin(phi);
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          zc val(1.0, 0.0);
+          for (int k = 0; k < w; ++k) {
+            int bi = (i >> k) & 1, bj = (j >> k) & 1;
+            val *= (bi == bj) ? zc(c, 0.0) : zc(0.0, -s);
+          }
+          u[i * d + j] = val;
+        }
+      return u;
+    };
+    std::vector<zc> dintra(d);
+    for (int s = 0; s < d; ++s) dintra[s] = std::exp(zc(0.0, -p.J * p.dt * energy_intra[b][s]));
+    auto full = xlayer(p.h * p.dt), half = xlayer(0.5 * p.h * p.dt);
+    p.site_gate[0][b].resize(d * d);
+    p.site_gate[1][b].resize(d * d);
+    p.site_gate[2][b] = half;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        p.site_gate[0][b][i * d + j] = full[i * d + j] * dintra[j];  // U_X * D_intra
+        p.site_gate[1][b][i * d + j] = dintra[i] * half[i * d + j];  // D_intra * U_X(half)
+      }
+    p.zsum[b].resize(d);
+    for (int s = 0; s < d; ++s) {
+      double z = 0;
+      for (int k = 0; k < w; ++k) z += zval(s, w, k);
+      p.zsum[b][s] = z;
+    }
+  }
+  // bond caps (valid for any block order): min(chi, dmax^p, dmax^(N-p))
+  p.cap.assign(p.N + 1, 1);
+  for (int b = 1; b < p.N; ++b) {
+    double lim = std::min((double)p.chi, std::min(std::pow((double)p.dmax, b),
+                                                   std::pow((double)p.dmax, p.N - b)));
+    p.cap[b] = (int)lim;
+  }
+}
+
+}  // namespace mpsim

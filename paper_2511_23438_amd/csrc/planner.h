@@ -1,0 +1,56 @@
+// Host-side planning of a block-MPS instance: grid geometry, half-row blocks,
+// snake order, the block-pair update schedule, gate tables and buffer sizes.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/mpsim.h"
+
+namespace mpsim {
+
+typedef std::complex<double> zc;
+
+struct Op {          // one entry of the step schedule
+  int kind;          // 1 = two-site update, 2 = single-site gate
+  int site;
+  int swap;          // kind 1
+  int gate;          // kind 1: block-pair phase applied
+  int variant;       // kind 2
+  int block_a, block_b;  // blocks at site, site+1 before the op (kind 1); block (kind 2)
+};
+
+struct Plan {
+  int R = 0, C = 0, n = 0, N = 0;  // grid, qubits, sites
+  int chi = 0, order = 1, periodic = 1;
+  double J = 0, h = 0, dt = 0, theta0 = 0;
+  int wL = 0, wR = 0, dmax = 1;
+  std::vector<int> block_width;               // per block id
+  std::vector<int> cap;                       // bond caps b_0..b_N
+  std::vector<std::vector<int>> block_qubits; // per block, in column order
+  std::vector<std::pair<int, int>> bonds;     // ZZ bonds (q1 < q2), each once
+
+  // gate tables: pair index of ordered (a, b) with a < b; -1 = not coupled
+  std::vector<int> pair_index;                // [a * nblocks + b]
+  std::vector<std::vector<zc>> pair_phase;    // [pair] d_a x d_b, row-major
+  std::vector<std::vector<zc>> site_gate[3];  // [variant][block] d x d
+  std::vector<std::vector<double>> zsum;      // [block] d entries
+
+  int nblocks() const { return 2 * R; }
+  int dim(int block) const { return 1 << block_width[block]; }
+  int coupled(int a, int b) const {
+    if (a == b) return -1;
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    return pair_index[lo * nblocks() + hi];
+  }
+  std::vector<int> snake() const;
+  // ops of one step from order `pos`; pos is updated to the end order
+  void step_ops(std::vector<int>& pos, std::vector<Op>& out) const;
+};
+
+// Validate a config; returns MPS_OK or an error code with a message.
+mps_status validate(const mps_config* cfg, const char** msg);
+// Build the plan (geometry, tables, caps) for a validated config.
+void build_plan(const mps_config* cfg, Plan& p);
+
+}  // namespace mpsim

@@ -1,0 +1,67 @@
+"""Host-side checks of the C-ABI library (no GPU needed): every symbol the
+header declares is exported, the step schedule equals the oracle's own,
+invalid configurations are rejected, and the admission footprint is sane."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.lattice import Grid
+from oracle.schedule import schedule as oracle_schedule
+from paper_2511_23438_amd import mpsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mpsim.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mps_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(mpsim._lib, n), n
+        assert n in mpsim.EXPORTED, n
+
+
+@pytest.mark.parametrize("R,C", [(4, 4), (5, 6), (6, 8), (7, 8), (3, 3), (4, 5), (1, 4),
+                                 (2, 3), (5, 5)])
+@pytest.mark.parametrize("order", [1, 2])
+def test_schedule_equals_oracle(R, C, order):
+    cfg = mpsim.make_config(R, C, 16, order=order)
+    got = mpsim.schedule_dump(cfg, 3)
+    ref = oracle_schedule(Grid(R, C), 3, order)
+    assert len(got) == len(ref)
+    for row, op in zip(got, ref):
+        if op[0] == "U2":
+            assert tuple(row) == (1, op[1], op[2], op[3], op[4], op[5])
+        else:
+            assert tuple(row[:4]) == (2, op[1], op[2], op[3])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(cols=1), mpsim.MPS_E_INVAL), (dict(rows=0), mpsim.MPS_E_INVAL),
+    (dict(cols=9), mpsim.MPS_E_UNSUPPORTED), (dict(chi=0), mpsim.MPS_E_INVAL),
+    (dict(order=3), mpsim.MPS_E_INVAL), (dict(schedule=2), mpsim.MPS_E_UNSUPPORTED)])
+def test_invalid_config_rejected(kw, status):
+    args = dict(rows=4, cols=4, chi=16)
+    args.update(kw)
+    cfg = mpsim.make_config(**args)
+    with pytest.raises(mpsim.MpsError) as e:
+        mpsim.footprint_bytes(cfg)
+    assert e.value.status == status
+    with pytest.raises(mpsim.MpsError):
+        mpsim.schedule_dump(cfg, 1)
+
+
+def test_footprint_monotone_and_fits():
+    fp = [mpsim.footprint_bytes(mpsim.make_config(6, 8, chi)) for chi in (256, 512, 1024)]
+    assert fp[0] < fp[1] < fp[2]
+    # sites alone: 7 bulk sites of chi*16*chi complex128
+    assert fp[2] > 7 * 1024 * 16 * 1024 * 16
+    assert fp[2] < 288 * 2 ** 30
