@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Trotter steps per second of the block-MPS evolution of the periodic 6x8
+transverse-field Ising grid (two half-row blocks of 4 qubits per row: d = 16,
+12 sites) at bond dimension chi = 1024, on one MI355X.
+
+One step = one whole Trotter step of the hot path: every two-site update of
+the block-pair schedule (contraction with the gate, Gram matrix, top-chi
+eigenspace, truncation, fidelity), the single-site layer, and one
+measurement of <Z_tot>, <Z_tot^2> and F_MPS. The state starts as the paper's
+product state (theta0 = pi/18, J = -1, h = 2, dt = 0.25); `--warmup` steps
+bring the bonds to their saturated sizes before the timed steps.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Trotter steps/sec at 6x8 χ=1024 (MFMA %); p50/p99 step latency served"
+PEAK = {"hbm": (8000.0, "GB/s"), "fp64": (78.6, "TFLOP/s")}
+# kernel class timed for the roofline line and its bound
+DOMINANT = {"trd_hemv": "hbm", "gram": "fp64", "gemm": "fp64", "theta": "fp64"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("linalg.hip", "gemm.hip"):
+        with open(os.path.join(ROOT, "paper_2511_23438_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kind: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, valid
+    only while the kernel sources still hash to the value it records."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kind, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("traffic_") and "=" in line:
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("traffic_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float) -> dict:
+    """Oracle (numpy, float64) timed on a bounded sample of the workload: one
+    bulk two-site update of the same grid at a reduced bond dimension,
+    extrapolated to chi by the cubic cost of its SVD and summed over the
+    updates of one steady-state step."""
+    import numpy as np
+    from oracle import mps as omps
+    from oracle.lattice import Grid
+    from oracle.schedule import step_ops
+    from paper_2511_23438_amd import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    d = 2 ** ((cols + 1) // 2)
+    g = Grid(rows, cols)
+    timed = None
+    chi_s = 64
+    while True:
+        sites, centre = workloads.random_mps(rows, cols, chi_s, 99)
+        m = omps.BlockMPS.from_sites(g, chi_s, sites, centre, -1.0, 2.0, 0.25)
+        i = rows - 1  # a bulk site pair
+        m.move_centre(i)
+        t0 = time.perf_counter()
+        m.apply_u2(i, False, True)
+        dt = time.perf_counter() - t0
+        kg = min(sites[i].shape[0] * d, d * sites[i + 1].shape[2])
+        timed = (chi_s, kg, dt)
+        log("cpu baseline sample: chi_s=%d kg=%d update %.2fs" % (chi_s, kg, dt))
+        if dt * 8 > budget_s or chi_s * 2 > chi:
+            break
+        chi_s *= 2
+    chi_s, kg_s, t_s = timed
+    # steady-state kg of every update in one step at the target chi
+    N = 2 * rows
+    caps = [1] + [int(min(chi, d ** b, d ** (N - b))) for b in range(1, N)] + [1]
+    step_s = 0.0
+    nup = 0
+    for op in step_ops(g, g.snake()):
+        if op[0] != "U2":
+            continue
+        i = op[1]
+        kg = min(caps[i] * d, d * caps[i + 2])
+        step_s += t_s * (kg / kg_s) ** 3
+        nup += 1
+    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": ("one bulk two-site update (numpy SVD) of the %dx%d grid at chi=%d "
+                       "(Gram side %d) took %.2fs; scaled by (kg/%d)^3 over the %d updates "
+                       "of a saturated chi=%d step" % (rows, cols, chi_s, kg_s, t_s, kg_s, nup,
+                                                       chi))}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rows", type=int, default=6)
+    ap.add_argument("--cols", type=int, default=8)
+    ap.add_argument("--chi", type=int, default=1024)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "c64", "bf16x3"])
+    ap.add_argument("--theta0", type=float, default=math.pi / 18)
+    ap.add_argument("--prof", default="trd_hemv", choices=sorted(DOMINANT))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("this build runs one MPS instance on one GPU; multi-GPU runs are not "
+              "supported (--gpus must be 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2511_23438_amd import mpsim
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    cfg = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
+                            precision=args.precision)
+    sim = mpsim.Simulation(cfg)
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        sim.step(1)
+        sim.sync()
+        log("warmup step %d: %.2fs bonds %s" % (w + 1, time.perf_counter() - t0, sim.bond_dims()))
+
+    sim.profile(args.prof)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sim.step(1)
+        obs = sim.measure()          # part of the step: one measurement per step
+        log("step %d: %.2fs since start, <Z>=%.6f <Z^2>=%.6f F=%.4e bonds %s" % (
+            k + 1, time.perf_counter() - t0, obs["z"], obs["z2"], obs["fidelity"],
+            sim.bond_dims()))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_k, launches, work = sim.profile_read()
+    sim.profile("off")
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+
+    bound = DOMINANT[args.prof]
+    peak, unit = PEAK[bound]
+    avg_s = (ms_k / 1e3) / max(launches, 1)
+    per_launch = work / max(launches, 1)
+    if bound == "hbm":
+        achieved = per_launch / avg_s / 1e9
+    else:
+        achieved = per_launch / avg_s / 1e12
+    workload = "tfim_%dx%d_chi%d" % (args.rows, args.cols, args.chi)
+    traffic = read_traffic(args.prof, workload)
+    roof = {"bound": "hbm" if bound == "hbm" else "mfma", "achieved": achieved, "peak": peak,
+            "unit": unit, "frac": achieved / peak, "traffic": traffic,
+            "kernel": args.prof, "launches": launches, "avg_launch_us": avg_s * 1e6,
+            "work_per_launch": per_launch,
+            "kernel_time_share": (ms_k / 1e3) / elapsed}
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "c64": "c64", "bf16x3": "bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": workload, "rows": args.rows, "cols": args.cols,
+                   "d": 2 ** ((args.cols + 1) // 2), "sites": 2 * args.rows, "chi": args.chi,
+                   "precision": args.precision, "theta0": args.theta0, "J": -1.0, "h": 2.0,
+                   "dt": 0.25, "trotter_order": 1, "schedule": "block-pair",
+                   "start": "product state + %d warmup steps" % args.warmup},
+        "roofline": roof,
+        "observables": {"z": obs["z"], "z2": obs["z2"], "fidelity": obs["fidelity"],
+                        "norm": obs["norm"]},
+    }
+    sim.free()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -187,6 +187,26 @@ mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t
 /* Synchronise the handle's stream and report any pending device error. */
 mps_status mps_sync(mps_handle h);
 
+/* Launch classes that mps_profile can time. */
+typedef enum {
+  MPS_PROF_OFF = 0,
+  MPS_PROF_TRD_HEMV = 1,  /* Hermitian mat-vec of the tridiagonalisation; work = bytes of the
+                             lower triangle read (16 B per complex element) */
+  MPS_PROF_GRAM = 2,      /* Gram GEMM of the truncation; work = 8 flops per complex MAC of the
+                             lower half */
+  MPS_PROF_GEMM = 3,      /* every complex GEMM; work = 8 M N K flops (half when lower-only) */
+  MPS_PROF_THETA = 4      /* two-site contraction with the gate epilogue; work = 8 M N K flops */
+} mps_prof_kind;
+
+/* Start timing every later launch of one class with HIP events recorded on
+ * the handle's stream (kind 0 stops); resets the accumulated totals.
+ * Diagnostic: adds two event records per timed launch. */
+mps_status mps_profile(mps_handle h, int32_t kind);
+
+/* Accumulated device time (ms), number of timed launches and their
+ * algorithmic work (bytes or flops, per the class). Synchronises. */
+mps_status mps_profile_read(mps_handle h, double* total_ms, int64_t* launches, double* work);
+
 /* Last error message of the handle (thread-local message if h == NULL). */
 const char* mps_last_error(mps_handle h);
 

@@ -46,6 +46,16 @@ class BlockMPS:
         self.update_log: list[dict] = []     # per-U2 diagnostics
         self._pair_cache: dict = {}
 
+    @classmethod
+    def from_sites(cls, grid: Grid, chi: int, sites, centre: int, J: float, h: float,
+                   dt: float, order: int = 1) -> "BlockMPS":
+        """Start from given sites (snake block order, mixed canonical form
+        with the norm on site ``centre``)."""
+        m = cls(grid, chi, 0.0, J, h, dt, order)
+        m.sites = [np.array(a, dtype=np.complex128) for a in sites]
+        m.centre = int(centre)
+        return m
+
     # ---- gates ---------------------------------------------------------
     def _pair(self, a: int, b: int) -> np.ndarray:
         key = (a, b)

@@ -1,6 +1,7 @@
 // Complex float64 GEMM on gfx950 MFMA (v_mfma_f64_16x16x4f64).
 #pragma once
 #include "common.h"
+#include "prof.h"
 
 namespace mpsim {
 
@@ -23,17 +24,20 @@ struct ZGemm {
   int transC;       // logical (i, j) stored at transC ? C[j*ldc + i] : C[i*ldc + j]
   cplx alpha, beta;
   int lower_only;   // skip output tiles strictly above the diagonal
+  int upper_only;   // skip output tiles strictly below the diagonal
   int epi;          // EPI_STORE or EPI_THETA
   // theta epilogue: row = a*d1 + s1, col = s2*b2 + g; value *= phase[s1][s2]
   // (phase_trans: phase[s2][s1]); swap: store at (a*d2 + s2, s1*b2 + g), ld d1*b2
   const cplx* phase;
   int phase_trans, d1, d2, b2, swap;
+  int tag;          // launch class for the profiler (PROF_GRAM, PROF_THETA or 0)
 };
 
 // C = alpha*op(A)*op(B) + beta*C (or the theta epilogue). `partial` is a
 // workspace of at least `partial_elems` complex values used for split-K on
 // skinny outputs (may be NULL to disable split-K).
-void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s);
+void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s,
+           Prof* prof = nullptr);
 
 inline ZGemm zgemm_args(int M, int N, int K, ZOp A, ZOp B, cplx* C, long ldc, int transC,
                         cplx alpha, cplx beta) {

@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
   __shared__ double Bs[2][BK][BN];
   const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
   if (g.lower_only && n0 >= m0 + BM) return;
+  if (g.upper_only && m0 >= n0 + BN) return;
   const int bz = blockIdx.z;
   const int bat = bz / gd.ksplit, ks = bz % gd.ksplit;
   const cplx* A = g.A.p + (long)bat * g.A.stride;
@@ -223,8 +224,19 @@ __global__ void zgemm_reduce(ZGemmDev gd) {
   }
 }
 
-void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Prof* prof) {
+  if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return;
+  ZGemm g = g0;
+  if (g.transC && g.epi == EPI_STORE) {
+    // A column-major result is stored as C^T = op(B)^T op(A)^T, row-major,
+    // so that neighbouring lanes write neighbouring addresses.
+    std::swap(g.A, g.B);
+    g.A.trans ^= 1;
+    g.B.trans ^= 1;
+    std::swap(g.M, g.N);
+    g.transC = 0;
+    std::swap(g.lower_only, g.upper_only);
+  }
   ZGemmDev gd;
   gd.g = g;
   gd.ksplit = 1;
@@ -240,7 +252,8 @@ void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s) {
     hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(256), 0, s, z);
     return;
   }
-  if (partial && g.epi == EPI_STORE && !g.lower_only && tiles < 128 && g.K >= 1024) {
+  if (partial && g.epi == EPI_STORE && !g.lower_only && !g.upper_only && tiles < 128 &&
+      g.K >= 1024) {
     int ks = (int)std::min<long>(g.K / 256, (256 + tiles - 1) / tiles);
     while (ks > 1 && (long)ks * g.batch * g.M * g.N > partial_elems) --ks;
     if (ks > 1) {
@@ -251,6 +264,10 @@ void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s) {
   }
   dim3 grid(ceil_div(g.N, BN), ceil_div(g.M, BM), g.batch * gd.ksplit);
   const int ta = g.A.trans, tb = g.B.trans;
+  const int pk = (prof && prof->kind == PROF_GEMM) ? PROF_GEMM : g.tag;
+  double flops = 8.0 * g.M * (double)g.N * g.K * g.batch;
+  if (g.lower_only || g.upper_only) flops = 8.0 * g.M * (g.M + 1.0) * 0.5 * g.K * g.batch;
+  if (prof) prof->begin(pk, s);
   if (ta == 0 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(256), 0, s, gd);
   else if (ta == 0 && tb == 1) hipLaunchKernelGGL((zgemm_kernel<0, 1>), grid, dim3(256), 0, s, gd);
   else if (ta == 1 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<1, 0>), grid, dim3(256), 0, s, gd);
@@ -260,6 +277,7 @@ void zgemm(const ZGemm& g, cplx* partial, long partial_elems, hipStream_t s) {
     int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(zgemm_reduce, dim3(blocks, g.batch), dim3(256), 0, s, gd);
   }
+  if (prof) prof->end(pk, flops, s);
 }
 
 }  // namespace mpsim

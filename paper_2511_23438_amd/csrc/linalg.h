@@ -23,6 +23,9 @@ struct LinalgWork {
   cplx* qtau = nullptr;     // QR reflector scalars (max QR columns)
   double* e2 = nullptr;     // squared off-diagonal (nmax)
   cplx* dpart = nullptr;    // partial dot products (column steps)
+  cplx* tsum = nullptr;     // reduced column-step sums (2*TRD_NB + 1)
+  int* cnt = nullptr;       // completion counters (zero between launches)
+  long cnt_stride = 0;      // offset of the column-kernel counter in cnt
   double* npart = nullptr;  // partial norms (QR column steps)
   double* scal = nullptr;   // 16 doubles of scalars
   double* lam = nullptr;    // eigenvalues (qmax + 1), ascending
@@ -38,6 +41,7 @@ struct LinalgWork {
   cplx* gpart = nullptr;    // split-K partials
   long gpart_elems = 0;
   int* flag = nullptr;      // numeric failure flag (device)
+  Prof* prof = nullptr;     // optional launch timing
 };
 
 // Reduce Hermitian A (n x n, column-major, lower triangle referenced) to real

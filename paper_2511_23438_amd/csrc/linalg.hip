@@ -50,47 +50,90 @@ static ZOp strided_op(const cplx* base, long rs, long cs, int conj = 0) {
 }
 
 // ---------------------------------------------------------------------------
-// Tridiagonalisation (lower), panel of TRD_NB columns
+// Tridiagonalisation (lower), panels of TRD_NB columns, two launches per column:
+//   k_trd_col  : finish the previous column of the panel (scale its reflector,
+//                add alpha*v to its W column), apply the panel's earlier
+//                reflectors to column c, and reduce |x|^2, W^H x, V^H x;
+//   k_trd_hemv : reflector of column c, then y = A22 v on the lower-triangle
+//                tiles of the trailing matrix; the last workgroup to
+//                contribute to a 64-row block finalises that block of the new
+//                W column, and the last block finalised computes alpha.
+// scal: [0] beta [1,2] tau [3,4] scale [5,6] alpha of the latest column.
 #define TP (2 * TRD_NB + 1)
 
-__global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, const cplx* W, long ldw,
-                                                 int i0, int j, int c, cplx* tpart) {
+__global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, cplx* W, long ldw, int i0,
+                                                 int j, int c, const double* scal, cplx* tpart,
+                                                 cplx* tsum, int* cnt) {
   __shared__ cplx wrow[TRD_NB], vrow[TRD_NB];
+  __shared__ cplx sh[4 * TP];
+  __shared__ int last;
   const int t = threadIdx.x;
+  const cplx alpha = make_double2(scal[5], scal[6]);
+  const cplx scp = make_double2(scal[3], scal[4]);
   if (t < j) {
-    wrow[t] = cconj(W[(long)t * ldw + c]);
-    vrow[t] = cconj(A[(long)(i0 + t) * lda + c]);
+    cplx wv = W[(long)t * ldw + c];
+    if (t == j - 1) wv = cadd(wv, alpha);
+    wrow[t] = cconj(wv);
+    vrow[t] = (t == j - 1) ? make_double2(1.0, 0.0) : cconj(A[(long)(i0 + t) * lda + c]);
   }
   __syncthreads();
   const long r = c + (long)blockIdx.x * 256 + t;
-  cplx a = make_double2(0.0, 0.0);
+  cplx a = make_double2(0.0, 0.0), vprev = make_double2(0.0, 0.0), wfix = make_double2(0.0, 0.0);
   if (r < n) {
+    if (j > 0) {
+      if (r == c) {
+        vprev = make_double2(1.0, 0.0);
+        wfix = cadd(W[(long)(j - 1) * ldw + r], alpha);
+      } else {
+        vprev = cmul(A[(long)(c - 1) * lda + r], scp);
+        A[(long)(c - 1) * lda + r] = vprev;
+        wfix = cadd(W[(long)(j - 1) * ldw + r], cmul(alpha, vprev));
+        W[(long)(j - 1) * ldw + r] = wfix;
+      }
+    }
     a = A[(long)c * lda + r];
     for (int jj = 0; jj < j; ++jj) {
-      cplx v = A[(long)(i0 + jj) * lda + r];
-      cplx wv = W[(long)jj * ldw + r];
+      const cplx v = (jj == j - 1) ? vprev : A[(long)(i0 + jj) * lda + r];
+      const cplx wv = (jj == j - 1) ? wfix : W[(long)jj * ldw + r];
       a = csub(a, cadd(cmul(v, wrow[jj]), cmul(wv, vrow[jj])));
     }
     if (r == c) a.y = 0.0;
     A[(long)c * lda + r] = a;
   }
   const bool act = (r < n) && (r >= c + 2);
+  const int count = 1 + 2 * j;
   const int lane = t & 63, wv = t >> 6;
-  const long base = ((long)blockIdx.x * 4 + wv) * TP;
-  double nn = wave_sum(act ? cabs2(a) : 0.0);
-  if (lane == 0) tpart[base] = make_double2(nn, 0.0);
-  for (int jj = 0; jj < j; ++jj) {
-    cplx tw = make_double2(0.0, 0.0), tv = make_double2(0.0, 0.0);
+  // value k: 0 -> |x|^2, 1..j -> conj(W[r, jj]) x, j+1..2j -> conj(V[r, jj]) x
+  for (int kk = 0; kk < count; ++kk) {
+    cplx v = make_double2(0.0, 0.0);
     if (act) {
-      tw = cmulc(W[(long)jj * ldw + r], a);
-      tv = cmulc(A[(long)(i0 + jj) * lda + r], a);
+      if (kk == 0) {
+        v = make_double2(cabs2(a), 0.0);
+      } else {
+        const int jj = (kk <= j) ? kk - 1 : kk - 1 - j;
+        if (kk <= j) v = cmulc((jj == j - 1) ? wfix : W[(long)jj * ldw + r], a);
+        else v = cmulc((jj == j - 1) ? vprev : A[(long)(i0 + jj) * lda + r], a);
+      }
     }
-    tw = wave_csum(tw);
-    tv = wave_csum(tv);
-    if (lane == 0) {
-      tpart[base + 1 + jj] = tw;
-      tpart[base + 1 + TRD_NB + jj] = tv;
+    v = wave_csum(v);
+    if (lane == 0) sh[wv * TP + kk] = v;
+  }
+  __syncthreads();
+  for (int kk = t; kk < count; kk += blockDim.x)
+    tpart[(long)blockIdx.x * TP + kk] = cadd(cadd(sh[kk], sh[TP + kk]), cadd(sh[2 * TP + kk], sh[3 * TP + kk]));
+  __threadfence();
+  if (t == 0) last = (atomicAdd(cnt, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    for (int k = t; k < count; k += blockDim.x) {
+      cplx acc = make_double2(0.0, 0.0);
+      for (int b = 0; b < (int)gridDim.x; ++b) acc = cadd(acc, tpart[(long)b * TP + k]);
+      // layout of tsum: [0] |x|^2, [1 + jj] W^H x, [1 + TRD_NB + jj] V^H x
+      const int dst = (k == 0) ? 0 : (k <= j ? k : 1 + TRD_NB + (k - 1 - j));
+      tsum[dst] = acc;
     }
+    if (t == 0) *cnt = 0;
   }
 }
 
@@ -100,13 +143,15 @@ __device__ inline cplx trd_v(const cplx* A, long lda, int n, int c, long r, cplx
   return cmul(A[(long)c * lda + r], sc);
 }
 
-// y = A22 v over the lower-triangle tiles of the trailing matrix.
-__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, int c,
-                                                  const cplx* tpart, int nparts, cplx* P, int nt,
-                                                  double* scal) {
+__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, cplx* W, long ldw,
+                                                  int i0, int j, int c, const cplx* tsum, cplx* P,
+                                                  int nt, int* cnt, cplx* dpart, double* scal,
+                                                  double* d, double* e, cplx* tau) {
   __shared__ cplx vI[64], vJ[64];
   __shared__ cplx red[4][64];
-  __shared__ double sh[5];
+  __shared__ cplx t1[TRD_NB], t2[TRD_NB];
+  __shared__ int fin[2];
+  __shared__ double dsh[4];
   const int t = threadIdx.x;
   const long k = blockIdx.x;
   long I = (long)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
@@ -114,19 +159,15 @@ __global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda
   while ((I + 1) * (I + 2) / 2 <= k) ++I;
   const long J = k - I * (I + 1) / 2;
   const int o = c + 1;
-  if (t == 0) {
-    double xn = 0.0;
-    for (int p = 0; p < nparts; ++p) xn += tpart[(long)p * TP].x;
-    cplx alpha = A[(long)c * lda + o];
-    double beta;
-    cplx tau, sc;
-    reflector(alpha, xn, beta, tau, sc);
-    sh[0] = beta; sh[1] = tau.x; sh[2] = tau.y; sh[3] = sc.x; sh[4] = sc.y;
-    if (blockIdx.x == 0)
-      for (int u = 0; u < 5; ++u) scal[u] = sh[u];
+  double beta;
+  cplx tauv, sc;
+  reflector(A[(long)c * lda + o], tsum[0].x, beta, tauv, sc);
+  if (blockIdx.x == 0 && t == 0) {
+    scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = sc.x; scal[4] = sc.y;
+    tau[c] = tauv;
+    e[c] = beta;
+    d[c] = A[(long)c * lda + c].x;
   }
-  __syncthreads();
-  const cplx sc = make_double2(sh[3], sh[4]);
   if (t < 64) vI[t] = trd_v(A, lda, n, c, o + I * 64 + t, sc);
   else if (t < 128) vJ[t - 64] = trd_v(A, lda, n, c, o + J * 64 + (t - 64), sc);
   __syncthreads();
@@ -154,66 +195,76 @@ __global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda
   }
   red[cg][rr] = y;
   __syncthreads();
-  if (t < 64) {
-    cplx s = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
-    P[(I * nt + J) * 64 + t] = s;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_trd_w(int n, cplx* A, long lda, cplx* W, long ldw, int i0,
-                                               int j, int c, const cplx* tpart, int nparts,
-                                               const cplx* P, int nt, const double* scal,
-                                               cplx* dpart, double* d, double* e, cplx* tau) {
-  __shared__ cplx t1[TRD_NB], t2[TRD_NB];
-  const int t = threadIdx.x;
-  const int o = c + 1;
-  const cplx tauv = make_double2(scal[1], scal[2]);
-  const cplx sc = make_double2(scal[3], scal[4]);
-  if (t < j) {
-    cplx s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
-    for (int p = 0; p < nparts; ++p) {
-      s1 = cadd(s1, tpart[(long)p * TP + 1 + t]);
-      s2 = cadd(s2, tpart[(long)p * TP + 1 + TRD_NB + t]);
-    }
-    t1[t] = cadd(cconj(W[(long)t * ldw + o]), cmul(sc, s1));
-    t2[t] = cadd(cconj(A[(long)(i0 + t) * lda + o]), cmul(sc, s2));
-  }
+  if (t < 64) P[(I * nt + J) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
+  __threadfence();
   __syncthreads();
-  const long r = o + (long)blockIdx.x * 256 + t;
-  cplx y = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
-  if (r < n) {
-    const long I = (r - o) / 64, x = (r - o) % 64;
-    for (long Jb = 0; Jb < nt; ++Jb) y = cadd(y, P[(I * nt + Jb) * 64 + x]);
-    for (int jj = 0; jj < j; ++jj)
-      y = csub(y, cadd(cmul(A[(long)(i0 + jj) * lda + r], t1[jj]), cmul(W[(long)jj * ldw + r], t2[jj])));
-    y = cmul(tauv, y);
-    W[(long)j * ldw + r] = y;
-    v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
-    A[(long)c * lda + r] = v;
-  }
-  cplx dt = wave_csum(cmulc(y, v));
-  if ((t & 63) == 0) dpart[(long)blockIdx.x * 4 + (t >> 6)] = dt;
-  if (blockIdx.x == 0 && t == 0) {
-    tau[c] = tauv;
-    e[c] = scal[0];
-    d[c] = A[(long)c * lda + c].x;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_trd_w2(int n, const cplx* A, long lda, cplx* W, long ldw,
-                                                int j, int c, const cplx* dpart, int ndp,
-                                                const double* scal) {
-  __shared__ cplx alpha_s;
-  const int t = threadIdx.x;
   if (t == 0) {
-    cplx dsum = make_double2(0.0, 0.0);
-    for (int p = 0; p < ndp; ++p) dsum = cadd(dsum, dpart[p]);
-    const cplx tauv = make_double2(scal[1], scal[2]);
-    alpha_s = cscale(cmul(tauv, dsum), -0.5);
+    fin[0] = (atomicAdd(&cnt[I], 1) == nt - 1) ? 1 : 0;
+    fin[1] = (I != J && atomicAdd(&cnt[J], 1) == nt - 1) ? 1 : 0;
   }
   __syncthreads();
-  const long r = c + 1 + (long)blockIdx.x * 256 + t;
-  if (r < n) W[(long)j * ldw + r] = cadd(W[(long)j * ldw + r], cmul(alpha_s, A[(long)c * lda + r]));
+  if (!fin[0] && !fin[1]) return;
+  __threadfence();
+  if (t < j) {
+    t1[t] = cadd(cconj(W[(long)t * ldw + o]), cmul(sc, tsum[1 + t]));
+    t2[t] = cadd(cconj(A[(long)(i0 + t) * lda + o]), cmul(sc, tsum[1 + TRD_NB + t]));
+  }
+  __syncthreads();
+  for (int f = 0; f < 2; ++f) {
+    if (!fin[f]) continue;
+    const long X = (f == 0) ? I : J;
+    double dre = 0.0, dim = 0.0;
+    if (t < 64) {
+      const long r = o + X * 64 + t;
+      if (r < n) {
+        cplx yy = make_double2(0.0, 0.0);
+        for (long Jb = 0; Jb < nt; ++Jb) yy = cadd(yy, P[(X * nt + Jb) * 64 + t]);
+        for (int jj = 0; jj < j; ++jj)
+          yy = csub(yy, cadd(cmul(A[(long)(i0 + jj) * lda + r], t1[jj]), cmul(W[(long)jj * ldw + r], t2[jj])));
+        yy = cmul(tauv, yy);
+        W[(long)j * ldw + r] = yy;
+        const cplx v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
+        const cplx dt = cmulc(yy, v);
+        dre = dt.x;
+        dim = dt.y;
+      }
+    }
+    dre = block_sum(dre, dsh);
+    dim = block_sum(dim, dsh);
+    if (t == 0) {
+      dpart[X] = make_double2(dre, dim);
+      cnt[X] = 0;
+    }
+    __threadfence();
+    __syncthreads();
+    if (t == 0) {
+      if (atomicAdd(&cnt[nt], 1) == nt - 1) {
+        __threadfence();
+        cplx ds = make_double2(0.0, 0.0);
+        for (int b = 0; b < nt; ++b) ds = cadd(ds, dpart[b]);
+        const cplx al = cscale(cmul(tauv, ds), -0.5);
+        scal[5] = al.x;
+        scal[6] = al.y;
+        cnt[nt] = 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Last column of a panel: scale its reflector, store the unit entry and add
+// alpha*v to its W column (rows c+1..n-1).
+__global__ __launch_bounds__(256) void k_trd_finish(int n, cplx* A, long lda, cplx* W, long ldw, int j,
+                                                    int c, const double* scal) {
+  const cplx alpha = make_double2(scal[5], scal[6]);
+  const cplx sc = make_double2(scal[3], scal[4]);
+  const long r = c + 1 + (long)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  cplx v;
+  if (r == c + 1) v = make_double2(1.0, 0.0);
+  else v = cmul(A[(long)c * lda + r], sc);
+  A[(long)c * lda + r] = v;
+  W[(long)j * ldw + r] = cadd(W[(long)j * ldw + r], cmul(alpha, v));
 }
 
 __global__ void k_trd_last(int n, const cplx* A, long lda, double* d) {
@@ -227,19 +278,20 @@ void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
     for (int j = 0; j < ib; ++j) {
       const int c = i0 + j;
       const int nb1 = ceil_div(n - c, 256);
-      hipLaunchKernelGGL(k_trd_col, dim3(nb1), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c, w.tpart);
+      hipLaunchKernelGGL(k_trd_col, dim3(nb1), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c,
+                         (const double*)w.scal, w.tpart, w.tsum, w.cnt + w.cnt_stride);
       const int np = n - c - 1;
       const int nt = ceil_div(np, 64);
       const long ntiles = (long)nt * (nt + 1) / 2;
+      if (w.prof) w.prof->begin(PROF_TRD_HEMV, s);
       hipLaunchKernelGGL(k_trd_hemv, dim3((unsigned)ntiles), dim3(256), 0, s, n, (const cplx*)A, lda,
-                         c, (const cplx*)w.tpart, nb1 * 4, w.P, nt, w.scal);
-      const int nb4 = ceil_div(np, 256);
-      hipLaunchKernelGGL(k_trd_w, dim3(nb4), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c,
-                         (const cplx*)w.tpart, nb1 * 4, (const cplx*)w.P, nt, (const double*)w.scal,
-                         w.dpart, w.d, w.e, w.tau);
-      hipLaunchKernelGGL(k_trd_w2, dim3(nb4), dim3(256), 0, s, n, (const cplx*)A, lda, w.W, ldw, j, c,
-                         (const cplx*)w.dpart, nb4 * 4, (const double*)w.scal);
+                         w.W, ldw, i0, j, c, (const cplx*)w.tsum, w.P, nt, w.cnt, w.dpart, w.scal,
+                         w.d, w.e, w.tau);
+      if (w.prof) w.prof->end(PROF_TRD_HEMV, 16.0 * np * (np + 1.0) * 0.5, s);
     }
+    const int cl = i0 + ib - 1;
+    hipLaunchKernelGGL(k_trd_finish, dim3(ceil_div(n - cl - 1, 256)), dim3(256), 0, s, n, A, lda, w.W,
+                       ldw, ib - 1, cl, (const double*)w.scal);
     const int o2 = i0 + ib;
     if (o2 < n) {
       const int nn = n - o2;
@@ -249,13 +301,13 @@ void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
                             zop(w.W + o2, ldw, 0, 1), C, lda, 1, make_double2(-1.0, 0.0),
                             make_double2(1.0, 0.0));
       g1.lower_only = 1;
-      zgemm(g1, nullptr, 0, s);
+      zgemm(g1, nullptr, 0, s, w.prof);
       // C -= W V^H
       ZGemm g2 = zgemm_args(nn, nn, ib, zop(w.W + o2, ldw, 1),
                             zop(A + (long)i0 * lda + o2, lda, 0, 1), C, lda, 1,
                             make_double2(-1.0, 0.0), make_double2(1.0, 0.0));
       g2.lower_only = 1;
-      zgemm(g2, nullptr, 0, s);
+      zgemm(g2, nullptr, 0, s, w.prof);
     }
   }
   hipLaunchKernelGGL(k_trd_last, dim3(1), dim3(1), 0, s, n, (const cplx*)A, lda, w.d);
@@ -343,84 +395,102 @@ __device__ inline double hash_uniform(uint64_t seed, uint64_t a, uint64_t b) {
   return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
 }
 
-// One thread per wanted eigenvector; work arrays interleaved [i*q + kq].
-__global__ void k_invit(int n, const double* d, const double* e, int q, const double* lam,
-                        int lam_off, const double* bounds, double* work, cplx* X, long ldx,
-                        uint64_t seed) {
+// One thread per wanted eigenvector; factor arrays interleaved [i*q + kq] so
+// that neighbouring threads touch neighbouring addresses. The recurrences of
+// the factorisation and of the two triangular solves carry their running
+// values in registers; memory holds only the factors and the vector.
+__global__ __launch_bounds__(64) void k_invit(int n, const double* d, const double* e, int q,
+                                              const double* lam, int lam_off, const double* bounds,
+                                              double* work, cplx* X, long ldx, uint64_t seed) {
   const int kq = blockIdx.x * blockDim.x + threadIdx.x;
   if (kq >= q) return;
   const long nq = (long)n * q;
-  double* dl = work;
-  double* dd = work + nq;
-  double* du = work + 2 * nq;
-  double* du2 = work + 3 * nq;
-  double* xx = work + 4 * nq;
-  double* pv = work + 5 * nq;
+  double* fl = work;            // multipliers
+  double* fd = work + nq;       // pivots (diagonal of U)
+  double* fu = work + 2 * nq;   // first superdiagonal of U
+  double* fu2 = work + 3 * nq;  // second superdiagonal of U
+  double* xx = work + 4 * nq;   // vector
+  double* pv = work + 5 * nq;   // 1 where rows i, i+1 were interchanged
 #define AT(arr, i) arr[(long)(i) * q + kq]
   const double lmb = lam[lam_off + q - 1 - kq];
   double epsp = DBL_EPSILON * bounds[2];
   if (epsp == 0.0) epsp = DBL_MIN;
-  for (int i = 0; i < n; ++i) {
-    AT(dd, i) = d[i] - lmb;
-    if (i < n - 1) {
-      AT(dl, i) = e[i];
-      AT(du, i) = e[i];
-      AT(du2, i) = 0.0;
-    }
-  }
-  // LU with partial pivoting of the tridiagonal T - lmb I
+  // LU with partial pivoting of T - lmb I. Running row i: (di, ui) pending,
+  // the next row's sub/diag/super come from d, e.
+  double di = d[0] - lmb;
+  double ui = (n > 1) ? e[0] : 0.0;
   for (int i = 0; i < n - 1; ++i) {
-    const double di = AT(dd, i), li = AT(dl, i);
+    const double li = e[i];
+    const double dn = d[i + 1] - lmb;
+    const double un = (i < n - 2) ? e[i + 1] : 0.0;
     if (fabs(di) >= fabs(li)) {
-      double fact = (di != 0.0) ? li / di : 0.0;
-      AT(dl, i) = fact;
-      AT(dd, i + 1) = AT(dd, i + 1) - fact * AT(du, i);
+      const double fact = (di != 0.0) ? li / di : 0.0;
+      AT(fl, i) = fact;
+      AT(fd, i) = di;
+      AT(fu, i) = ui;
+      AT(fu2, i) = 0.0;
       AT(pv, i) = 0.0;
+      di = dn - fact * ui;
+      ui = un;
     } else {
       const double fact = di / li;
-      AT(dd, i) = li;
-      AT(dl, i) = fact;
-      const double tmp = AT(du, i);
-      const double dnext = AT(dd, i + 1);
-      AT(du, i) = dnext;
-      AT(dd, i + 1) = tmp - fact * dnext;
-      if (i < n - 2) {
-        AT(du2, i) = AT(du, i + 1);
-        AT(du, i + 1) = -fact * AT(du, i + 1);
-      }
+      AT(fl, i) = fact;
+      AT(fd, i) = li;
+      AT(fu, i) = dn;
+      AT(fu2, i) = un;
       AT(pv, i) = 1.0;
+      di = ui - fact * dn;
+      ui = -fact * un;
     }
   }
-  for (int i = 0; i < n; ++i)
-    if (fabs(AT(dd, i)) < epsp) AT(dd, i) = (AT(dd, i) < 0.0) ? -epsp : epsp;
+  AT(fd, n - 1) = di;
+  for (int i = 0; i < n; ++i) {
+    const double v = AT(fd, i);
+    if (fabs(v) < epsp) AT(fd, i) = (v < 0.0) ? -epsp : epsp;
+  }
   for (int i = 0; i < n; ++i) AT(xx, i) = hash_uniform(seed, (uint64_t)kq, (uint64_t)i);
-  double nrm = 1.0;
   for (int it = 0; it < 3; ++it) {
+    // forward: apply the row interchanges and multipliers
+    double cur = AT(xx, 0);
     for (int i = 0; i < n - 1; ++i) {
+      const double nxt = AT(xx, i + 1);
       if (AT(pv, i) == 0.0) {
-        AT(xx, i + 1) = AT(xx, i + 1) - AT(dl, i) * AT(xx, i);
+        AT(xx, i) = cur;
+        cur = nxt - AT(fl, i) * cur;
       } else {
-        const double tmp = AT(xx, i);
-        AT(xx, i) = AT(xx, i + 1);
-        AT(xx, i + 1) = tmp - AT(dl, i) * AT(xx, i);
+        AT(xx, i) = nxt;
+        cur = cur - AT(fl, i) * nxt;
       }
     }
-    AT(xx, n - 1) = AT(xx, n - 1) / AT(dd, n - 1);
-    if (n > 1) AT(xx, n - 2) = (AT(xx, n - 2) - AT(du, n - 2) * AT(xx, n - 1)) / AT(dd, n - 2);
-    for (int i = n - 3; i >= 0; --i)
-      AT(xx, i) = (AT(xx, i) - AT(du, i) * AT(xx, i + 1) - AT(du2, i) * AT(xx, i + 2)) / AT(dd, i);
-    double mx = 0.0;
-    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(AT(xx, i)));
+    AT(xx, n - 1) = cur;
+    // backward: upper triangular with two superdiagonals
+    double x1 = AT(xx, n - 1) / AT(fd, n - 1);
+    AT(xx, n - 1) = x1;
+    double x2 = 0.0;
+    if (n > 1) {
+      const double v = (AT(xx, n - 2) - AT(fu, n - 2) * x1) / AT(fd, n - 2);
+      AT(xx, n - 2) = v;
+      x2 = x1;
+      x1 = v;
+    }
+    double mx = fmax(fabs(x1), fabs(x2));
+    for (int i = n - 3; i >= 0; --i) {
+      const double v = (AT(xx, i) - AT(fu, i) * x1 - AT(fu2, i) * x2) / AT(fd, i);
+      AT(xx, i) = v;
+      x2 = x1;
+      x1 = v;
+      mx = fmax(mx, fabs(v));
+    }
     if (!(mx > 0.0) || !isfinite(mx)) mx = 1.0;
     double s2 = 0.0;
     for (int i = 0; i < n; ++i) {
       const double v = AT(xx, i) / mx;
-      AT(xx, i) = v;
       s2 += v * v;
     }
-    nrm = sqrt(s2);
+    double nrm = sqrt(s2);
     if (!(nrm > 0.0)) nrm = 1.0;
-    for (int i = 0; i < n; ++i) AT(xx, i) = AT(xx, i) / nrm;
+    const double sc = 1.0 / (mx * nrm);
+    for (int i = 0; i < n; ++i) AT(xx, i) = AT(xx, i) * sc;
   }
   for (int i = 0; i < n; ++i) X[(long)i * ldx + kq] = make_double2(AT(xx, i), 0.0);
 #undef AT
@@ -489,7 +559,7 @@ static void block_reflector(const cplx* A, long rs, long cs, int row0, int col0,
   // S = V^H V (ib x ib, ld 64)
   ZGemm g = zgemm_args(ib, ib, mrows, zop(w.V, ldv, 0, 1), zop(w.V, ldv, 1), w.S, 64, 0,
                        make_double2(1.0, 0.0), make_double2(0.0, 0.0));
-  zgemm(g, w.gpart, w.gpart_elems, s);
+  zgemm(g, w.gpart, w.gpart_elems, s, w.prof);
   hipLaunchKernelGGL(k_larft, dim3(1), dim3(64), 0, s, ib, (const cplx*)w.S, tau, T);
 }
 
@@ -503,16 +573,16 @@ static void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, i
   // W1 = V^H C (ib x ncols, ld wmax)
   ZGemm g1 = zgemm_args(ib, ncols, mrows, zop(w.V, ldv, 0, 1), strided_op(C, rs, cs), w.W1, w.wmax,
                         0, one, zero);
-  zgemm(g1, w.gpart, w.gpart_elems, s);
+  zgemm(g1, w.gpart, w.gpart_elems, s, w.prof);
   // W2 = op(T) W1
   ZGemm g2 = zgemm_args(ib, ncols, ib, tconj ? zop(T, 64, 1, 1) : zop(T, 64, 0), zop(w.W1, w.wmax, 0),
                         w.W2, w.wmax, 0, one, zero);
-  zgemm(g2, nullptr, 0, s);
+  zgemm(g2, nullptr, 0, s, w.prof);
   // C -= V W2
   ZOp cop = strided_op(C, rs, cs);
   ZGemm g3 = zgemm_args(mrows, ncols, ib, zop(w.V, ldv, 1), zop(w.W2, w.wmax, 0), C, cop.ld,
                         cop.trans, make_double2(-1.0, 0.0), one);
-  zgemm(g3, nullptr, 0, s);
+  zgemm(g3, nullptr, 0, s, w.prof);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,6 +20,7 @@
 #include "linalg.h"
 #include "mps_kernels.h"
 #include "planner.h"
+#include "prof.h"
 
 using namespace mpsim;
 
@@ -52,6 +53,7 @@ struct mps_sim {
   double* flog = nullptr;
   long log_cap = 0, nlog = 0;
   LinalgWork lw;
+  Prof prof;
 
   cplx* d_pairs = nullptr;
   std::vector<long> pair_off;
@@ -146,7 +148,7 @@ LwSizes lw_sizes(const Sizes& z) {
   l.tpart = std::max(nparts * (2 * TRD_NB + 1), nparts * QR_NB);
   long nt = ceil_div(z.nmax, 64);
   l.P = nt * nt * 64;
-  l.dpart = nparts;
+  l.dpart = std::max(nparts, nt + 1);
   l.npart = nparts;
   l.iwork = 6 * z.nmax * z.qmax;
   l.T = ((long)z.colmax / QR_NB + 2) * 4096;
@@ -167,6 +169,13 @@ size_t footprint(const Plan& p) {
   total += (size_t)(l.npart + l.iwork + 4 * z.nmax + z.qmax + 2 + 16 + 2 * 4096) * d;
   total += (size_t)(z.nmax + z.colmax) * c;
   return total;
+}
+
+// Stream-ordered copy followed by a wait on the handle's stream only.
+hipError_t copy_sync(mps_sim* h, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return e;
 }
 
 mps_status fail(mps_sim* h, mps_status st, const std::string& msg) {
@@ -211,7 +220,7 @@ void move_right(mps_sim* h) {
   // site c+1 <- R * site c+1  (kmin x k) (k x d2*b2)
   ZGemm g = zgemm_args(kmin, d2 * b2, k, zop(h->tmpB, k, 0), zop(h->site[c + 1], (long)d2 * b2, 0),
                        h->tmpC, (long)d2 * b2, 0, make_double2(1, 0), make_double2(0, 0));
-  zgemm(g, h->lw.gpart, h->lw.gpart_elems, s);
+  zgemm(g, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
   HIPCHK(hipMemcpyAsync(h->site[c + 1], h->tmpC, sizeof(cplx) * (size_t)kmin * d2 * b2,
                         hipMemcpyDeviceToDevice, s));
   h->bond[c + 1] = kmin;
@@ -237,7 +246,7 @@ void move_left(mps_sim* h) {
   // site c-1 <- site c-1 * R^H : (bp*dp x k) (k x kmin)
   ZGemm g = zgemm_args(bp * dp, kmin, k, zop(h->site[c - 1], k, 0), zop(h->tmpB, k, 1, 1), h->tmpC,
                        kmin, 0, make_double2(1, 0), make_double2(0, 0));
-  zgemm(g, h->lw.gpart, h->lw.gpart_elems, s);
+  zgemm(g, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
   HIPCHK(hipMemcpyAsync(h->site[c - 1], h->tmpC, sizeof(cplx) * (size_t)bp * dp * kmin,
                         hipMemcpyDeviceToDevice, s));
   h->bond[c] = kmin;
@@ -270,6 +279,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   g.epi = EPI_THETA;
   g.d1 = d1; g.d2 = d2; g.b2 = b2; g.swap = swap;
   g.phase = nullptr;
+  g.tag = PROF_THETA;
   if (gate) {
     int pi = p.coupled(ba, bb);
     if (pi >= 0) {
@@ -277,7 +287,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
       g.phase_trans = (ba > bb) ? 1 : 0;
     }
   }
-  zgemm(g, nullptr, 0, s);
+  zgemm(g, nullptr, 0, s, &h->prof);
   norm2(h, h->theta, mo * no, 2);
 
   bool left;
@@ -292,12 +302,13 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     ZGemm gg = zgemm_args(kg, kg, (int)no, zop(h->theta, no, 0), zop(h->theta, no, 1, 1), h->gram, kg, 1,
                           one, zero);
     gg.lower_only = 1;
-    zgemm(gg, nullptr, 0, s);
+    gg.tag = PROF_GRAM;
+    zgemm(gg, nullptr, 0, s, &h->prof);
     heev_top(kg, h->gram, kg, q, h->site[i], q, h->tmpA, h->lw, seed, s);
     // C = U^H M -> site i+1 (q x no)
     ZGemm gc = zgemm_args(q, (int)no, kg, zop(h->site[i], q, 1, 1), zop(h->theta, no, 0), h->site[i + 1],
                           no, 0, one, zero);
-    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s);
+    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i + 1], (long)q * no, 3);
     ensure_log(h, h->nlog + 1);
     launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
@@ -309,13 +320,14 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     ZGemm gg = zgemm_args(kg, kg, (int)mo, zop(h->theta, no, 1, 1), zop(h->theta, no, 0), h->gram, kg, 1,
                           one, zero);
     gg.lower_only = 1;
-    zgemm(gg, nullptr, 0, s);
+    gg.tag = PROF_GRAM;
+    zgemm(gg, nullptr, 0, s, &h->prof);
     heev_top(kg, h->gram, kg, q, h->tmpB, q, h->tmpA, h->lw, seed, s);
     launch_conj_transpose(h->tmpB, kg, q, q, h->site[i + 1], kg, s);
     // C = M V -> site i (mo x q)
     ZGemm gc = zgemm_args((int)mo, q, kg, zop(h->theta, no, 0), zop(h->tmpB, q, 0), h->site[i], q, 0, one,
                           zero);
-    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s);
+    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i], mo * q, 3);
     ensure_log(h, h->nlog + 1);
     launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
@@ -357,7 +369,8 @@ mps_status check_device(mps_sim* h) {
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(h, MPS_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
   int flag = 0;
-  e = hipMemcpy(&flag, h->lw.flag, sizeof(int), hipMemcpyDeviceToHost);
+  e = hipMemcpyAsync(&flag, h->lw.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(h, MPS_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
   if (flag) return fail(h, MPS_E_NUMERIC, "non-finite or zero norm in a truncation");
   return MPS_OK;
@@ -380,7 +393,7 @@ void measure_sweep(mps_sim* h, double out[3]) {
     g1.A.stride = (long)b * b;
     g1.B.stride = 0;
     g1.strideC = xs;
-    zgemm(g1, nullptr, 0, s);
+    zgemm(g1, nullptr, 0, s, &h->prof);
     launch_meas_combine(h->envx, b, d, b2, h->d_zsum + h->zsum_off[blk], s);
     // E'_k = A^H Y_k
     ZGemm g2 = zgemm_args(b2, b2, b * d, zop(h->site[st], b2, 1, 1), zop(h->envx, b2, 0), h->env[1 - cur], b2,
@@ -389,7 +402,7 @@ void measure_sweep(mps_sim* h, double out[3]) {
     g2.A.stride = 0;
     g2.B.stride = xs;
     g2.strideC = (long)b2 * b2;
-    zgemm(g2, nullptr, 0, s);
+    zgemm(g2, nullptr, 0, s, &h->prof);
     cur = 1 - cur;
   }
   cplx host[3];
@@ -409,15 +422,15 @@ void upload_product_state(mps_sim* h) {
       for (int j = 0; j < w; ++j) amp *= (((idx >> (w - 1 - j)) & 1) == 0) ? c : sn;
       v[idx] = make_double2(amp, 0.0);
     }
-    HIPCHK(hipMemcpy(h->site[st], v.data(), sizeof(cplx) * d, hipMemcpyHostToDevice));
+    HIPCHK(copy_sync(h, h->site[st], v.data(), sizeof(cplx) * d, hipMemcpyHostToDevice));
   }
 }
 
 void reset_bookkeeping(mps_sim* h) {
   double sc[5] = {0.0, INFINITY, 0.0, 0.0, 0.0};
-  HIPCHK(hipMemcpy(h->dscal, sc, sizeof(sc), hipMemcpyHostToDevice));
+  HIPCHK(copy_sync(h, h->dscal, sc, sizeof(sc), hipMemcpyHostToDevice));
   int zero = 0;
-  HIPCHK(hipMemcpy(h->lw.flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(copy_sync(h, h->lw.flag, &zero, sizeof(int), hipMemcpyHostToDevice));
   h->nlog = 0;
   h->steps = 0;
 }
@@ -504,6 +517,10 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     w.P = dalloc<cplx>(h, l.P);
     w.P_elems = l.P;
     w.dpart = dalloc<cplx>(h, l.dpart);
+    w.tsum = dalloc<cplx>(h, 2 * TRD_NB + 2);
+    w.cnt_stride = ceil_div(z.nmax, 64) + 8;
+    w.cnt = dalloc<int>(h, w.cnt_stride + 8);
+    HIPCHK(hipMemsetAsync(w.cnt, 0, sizeof(int) * (w.cnt_stride + 8), h->stream));
     w.npart = dalloc<double>(h, l.npart);
     w.d = dalloc<double>(h, z.nmax);
     w.e = dalloc<double>(h, z.nmax);
@@ -524,6 +541,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     w.gpart = dalloc<cplx>(h, l.gpart);
     w.gpart_elems = l.gpart;
     w.flag = dalloc<int>(h, 4);
+    w.prof = &h->prof;
     // gate tables
     long off = 0;
     for (auto& t : p.pair_phase) { h->pair_off.push_back(off); off += (long)t.size(); }
@@ -533,7 +551,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
       long o2 = 0;
       for (auto& t : p.pair_phase)
         for (auto& z2 : t) hp[o2++] = make_double2(z2.real(), z2.imag());
-      if (off) HIPCHK(hipMemcpy(h->d_pairs, hp.data(), sizeof(cplx) * off, hipMemcpyHostToDevice));
+      if (off) HIPCHK(copy_sync(h, h->d_pairs, hp.data(), sizeof(cplx) * off, hipMemcpyHostToDevice));
     }
     long goff = 0;
     std::vector<cplx> hg;
@@ -544,14 +562,14 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
         goff += (long)p.site_gate[v][b].size();
       }
     h->d_gates = dalloc<cplx>(h, goff);
-    HIPCHK(hipMemcpy(h->d_gates, hg.data(), sizeof(cplx) * goff, hipMemcpyHostToDevice));
+    HIPCHK(copy_sync(h, h->d_gates, hg.data(), sizeof(cplx) * goff, hipMemcpyHostToDevice));
     std::vector<double> hz;
     for (int b = 0; b < p.nblocks(); ++b) {
       h->zsum_off.push_back((long)hz.size());
       for (double zz : p.zsum[b]) hz.push_back(zz);
     }
     h->d_zsum = dalloc<double>(h, (long)hz.size());
-    HIPCHK(hipMemcpy(h->d_zsum, hz.data(), sizeof(double) * hz.size(), hipMemcpyHostToDevice));
+    HIPCHK(copy_sync(h, h->d_zsum, hz.data(), sizeof(double) * hz.size(), hipMemcpyHostToDevice));
     // state
     h->pos = p.snake();
     h->bond.assign(p.N + 1, 1);
@@ -560,7 +578,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->log_cap = 0;
     ensure_log(h, 64L * (11 * p.R + 4));
     reset_bookkeeping(h);
-    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipStreamSynchronize(h->stream));
   } catch (NoMem&) {
     mps_free(h);
     return fail(nullptr, MPS_E_NOMEM, "device allocation failed");
@@ -619,7 +637,7 @@ mps_status mps_measure(mps_handle h, double gamma, mps_obs* out) {
   double e[3];
   double sc[2];
   TRYDEV(h, measure_sweep(h, e);
-         HIPCHK(hipMemcpy(sc, h->dscal, sizeof(sc), hipMemcpyDeviceToHost)));
+         HIPCHK(copy_sync(h, sc, h->dscal, sizeof(sc), hipMemcpyDeviceToHost)));
   mps_status st = check_device(h);
   if (st != MPS_OK) return st;
   const double n = h->plan.n;
@@ -645,7 +663,7 @@ mps_status mps_fidelity(mps_handle h, double* fidelity, double* log_fidelity) {
   mps_status st = check_device(h);
   if (st != MPS_OK) return st;
   double sc = 0;
-  if (hipMemcpy(&sc, h->dscal, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+  if (copy_sync(h, &sc, h->dscal, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(h, MPS_E_DEVICE, "copy failed");
   *log_fidelity = sc;
   *fidelity = std::exp(sc);
@@ -689,7 +707,7 @@ mps_status mps_get_site(mps_handle h, int32_t p, double* re_im, int64_t cap, int
   if (cap < len || !re_im) return fail(h, MPS_E_INVAL, "buffer too small");
   mps_status st = check_device(h);
   if (st != MPS_OK) return st;
-  if (hipMemcpy(re_im, h->site[p], sizeof(cplx) * len, hipMemcpyDeviceToHost) != hipSuccess)
+  if (copy_sync(h, re_im, h->site[p], sizeof(cplx) * len, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(h, MPS_E_DEVICE, "copy failed");
   return MPS_OK;
 }
@@ -709,7 +727,7 @@ mps_status mps_set_state(mps_handle h, const int32_t* bonds, const double* const
     std::vector<int> pos = p.snake();
     for (int s = 0; s < p.N; ++s) {
       long len = (long)bonds[s] * p.dim(pos[s]) * bonds[s + 1];
-      HIPCHK(hipMemcpy(h->site[s], sites[s], sizeof(cplx) * len, hipMemcpyHostToDevice));
+      HIPCHK(copy_sync(h, h->site[s], sites[s], sizeof(cplx) * len, hipMemcpyHostToDevice));
     }
     h->pos = pos;
     h->bond.assign(bonds, bonds + p.N + 1);
@@ -735,7 +753,7 @@ mps_status mps_truncation_log(mps_handle h, double* f, double* gap, int32_t cap,
   if (st != MPS_OK) return st;
   std::vector<double> buf(2 * std::max<long>(h->nlog, 1));
   if (h->nlog > 0 &&
-      hipMemcpy(buf.data(), h->flog, sizeof(double) * 2 * h->nlog, hipMemcpyDeviceToHost) != hipSuccess)
+      copy_sync(h, buf.data(), h->flog, sizeof(double) * 2 * h->nlog, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(h, MPS_E_DEVICE, "copy failed");
   for (long k = 0; k < h->nlog; ++k) {
     f[k] = buf[2 * k];
@@ -759,7 +777,7 @@ mps_status mps_bond_spectrum(mps_handle h, int32_t bond, double* sv, int32_t cap
     ZGemm gg = zgemm_args(b1, b1, m, zop(h->site[c], b1, 1, 1), zop(h->site[c], b1, 0), h->gram, b1, 1,
                           make_double2(1, 0), make_double2(0, 0));
     gg.lower_only = 1;
-    zgemm(gg, nullptr, 0, h->stream);
+    zgemm(gg, nullptr, 0, h->stream, &h->prof);
     hetrd_lower(b1, h->gram, b1, h->lw, h->stream);
     tridiag_eigvals(b1, 0, b1, h->lw, h->stream);
     std::vector<double> lam(b1);
@@ -784,7 +802,7 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len) {
   for (int s = 0; s < p.N; ++s) {
     const int b0 = h->bond[s], d = p.dim(h->pos[s]), b1 = h->bond[s + 1];
     std::vector<zc> A((size_t)b0 * d * b1);
-    if (hipMemcpy(A.data(), h->site[s], sizeof(zc) * A.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    if (copy_sync(h, A.data(), h->site[s], sizeof(zc) * A.size(), hipMemcpyDeviceToHost) != hipSuccess)
       return fail(h, MPS_E_DEVICE, "copy failed");
     std::vector<zc> U((size_t)left * d * b1, zc(0, 0));
     for (long x = 0; x < left; ++x)
@@ -811,6 +829,25 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len) {
     re_im[2 * x] = T[flat].real();
     re_im[2 * x + 1] = T[flat].imag();
   }
+  return MPS_OK;
+}
+
+mps_status mps_profile(mps_handle h, int32_t kind) {
+  GUARD(h);
+  if (kind < PROF_OFF || kind > PROF_THETA) return fail(h, MPS_E_INVAL, "unknown launch class");
+  h->prof.reset(kind);
+  return MPS_OK;
+}
+
+mps_status mps_profile_read(mps_handle h, double* total_ms, int64_t* launches, double* work) {
+  GUARD(h);
+  if (!total_ms || !launches || !work) return fail(h, MPS_E_INVAL, "NULL output");
+  mps_status st = check_device(h);
+  if (st != MPS_OK) return st;
+  h->prof.flush();
+  *total_ms = h->prof.ms;
+  *launches = h->prof.launches;
+  *work = h->prof.work;
   return MPS_OK;
 }
 

@@ -17,6 +17,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpsim.so")
 
+# torch bundles its own HIP runtime (same soname, libamdhip64.so.7); loading
+# torch first makes the library bind to that runtime instead of starting a
+# second one in the same process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pure C-ABI use without torch
+    torch = None
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpsim.so not built: run `python -m paper_2511_23438_amd.build` "
                       "(or __graft_entry__.build())")
@@ -81,6 +89,9 @@ _sig = {
     "mps_to_statevector": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64]),
     "mps_apply_trotter_step_batched": (C.c_int, [C.POINTER(H), C.c_int32, C.c_int32]),
     "mps_sync": (C.c_int, [H]),
+    "mps_profile": (C.c_int, [H, C.c_int32]),
+    "mps_profile_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]),
     "mps_last_error": (C.c_char_p, [H]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -216,6 +227,17 @@ class Simulation:
             self.free()
         except Exception:
             pass
+
+    # -- profiling ----------------------------------------------------------
+    PROF = {"off": 0, "trd_hemv": 1, "gram": 2, "gemm": 3, "theta": 4}
+
+    def profile(self, kind: str) -> None:
+        _check(_lib.mps_profile(self.h, self.PROF[kind]), self.h)
+
+    def profile_read(self) -> tuple[float, int, float]:
+        ms, n, w = C.c_double(), C.c_int64(), C.c_double()
+        _check(_lib.mps_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(w)), self.h)
+        return ms.value, n.value, w.value
 
     # -- diagnostics --------------------------------------------------------
     def bond_dims(self) -> list[int]:

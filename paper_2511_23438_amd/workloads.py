@@ -96,3 +96,49 @@ def serving_trace(count: int = 200, rate: float = 50.0, seed: int = 2511,
             theta0=float(g.uniform(0.0, math.pi / 2)),
             steps=int(g.integers(10, 41)), precision="c64", name="req%d" % k)))
     return out
+
+
+def snake_dims(rows: int, cols: int) -> list[int]:
+    """Local dimension of each site in the initial snake order (even rows
+    left block first, odd rows right block first)."""
+    dl, dr = 2 ** ((cols + 1) // 2), 2 ** (cols // 2)
+    out = []
+    for r in range(rows):
+        out += [dl, dr] if r % 2 == 0 else [dr, dl]
+    return out
+
+
+def random_mps(rows: int, cols: int, chi: int, seed: int,
+               centre: int | None = None) -> tuple[list[np.ndarray], int]:
+    """Seeded random normalised MPS in mixed canonical form: sites left of
+    `centre` left-orthonormal, sites right of it right-orthonormal, the norm
+    on site `centre` (default: the last site); bonds at min(chi, products of
+    local dims).
+
+    A symmetry-free input state: the lattice symmetries of a uniform product
+    state give exactly degenerate Schmidt values, which make truncations
+    non-unique; a random state has none."""
+    g = rng(seed)
+    dims = snake_dims(rows, cols)
+    N = len(dims)
+    c = N - 1 if centre is None else int(centre)
+    bonds = [1]
+    for p in range(1, N):
+        left = int(np.prod(dims[:p], dtype=np.float64)) if p < 40 else 10 ** 12
+        right = int(np.prod(dims[p:], dtype=np.float64)) if N - p < 40 else 10 ** 12
+        bonds.append(int(min(chi, left, right)))
+    bonds.append(1)
+    sites = []
+    for p in range(N):
+        b0, d, b1 = bonds[p], dims[p], bonds[p + 1]
+        x = g.standard_normal((b0 * d, b1)) + 1j * g.standard_normal((b0 * d, b1))
+        if p < c:
+            q, _ = np.linalg.qr(x)
+            sites.append(q[:, :b1].reshape(b0, d, b1))
+        elif p > c:
+            y = x.reshape(b0, d * b1)
+            q, _ = np.linalg.qr(y.conj().T)
+            sites.append(q[:, :b0].conj().T.reshape(b0, d, b1))
+        else:
+            sites.append((x / np.linalg.norm(x)).reshape(b0, d, b1))
+    return sites, c

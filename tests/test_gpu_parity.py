@@ -52,14 +52,27 @@ def test_config_4x4_chi16_20_steps(seed):
     sim, ora, out = _run_pair(4, 4, 16, inst.theta0, 20)
     f_gpu, _ = sim.truncation_log()
     f_ora = np.array([u["f"] for u in ora.update_log])
-    err = max(max(abs(a["z"] - b["z"]), abs(a["z2"] - b["z2"]),
-                  abs(a["log_fidelity"] - b["log_fidelity"])) for a, b in out)
-    ferr = np.max(np.abs(f_gpu - f_ora))
-    print("4x4 chi16 seed", seed, "max obs err", err, "max f err", ferr)
+    gaps = np.array([u["gap"] for u in ora.update_log])
     assert len(f_gpu) == len(f_ora) == 20 * 32
-    if _gap_ok(ora):
-        assert err < TOL
-        assert ferr < TOL
+    # Until the first truncation whose cut falls inside a (numerically)
+    # degenerate multiplet, the truncated state is unique: both paths must
+    # agree there. From that update on several truncations are correct.
+    first_degenerate = int(np.argmax(gaps < 1e-8)) if np.any(gaps < 1e-8) else len(gaps)
+    ferr = np.abs(f_gpu - f_ora)
+    agree = ferr[:first_degenerate]
+    print("4x4 chi16 seed", seed, "first degenerate cut at update", first_degenerate,
+          "max f err before it", agree.max() if len(agree) else 0.0,
+          "max f err overall", ferr.max())
+    assert np.all(agree < TOL)
+    steps_clean = first_degenerate // 32
+    for s_, (a, b) in enumerate(out[:steps_clean + 1]):
+        assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
+    # what holds for every valid truncation sequence
+    for a, _ in out:
+        assert abs(a["norm"] - 1) < 1e-12 and a["fidelity"] <= 1.0
+        assert abs(a["z"]) <= 1 and a["z"] ** 2 <= a["z2"] + 1e-12 and a["z2"] <= 1 + 1e-12
+    assert np.all(f_gpu <= 1 + 1e-12)
     assert sim.bond_dims() == ora.bond_dims()
     assert sim.site_blocks() == ora.pos
 
@@ -129,3 +142,31 @@ def test_estimators():
     assert abs(o["z_rescaled"] - o["fidelity"] * o["z"]) < 1e-15
     assert abs(o["z2_rescaled"] - o["z2"] * o["fidelity"] ** 0.647) < 1e-15
     assert math.isnan(sim.measure()["z2_rescaled"])
+
+
+@pytest.mark.parametrize("R,C,chi,init_chi,steps,seed", [
+    (4, 4, 16, 16, 3, 11), (4, 4, 8, 8, 2, 12), (3, 5, 24, 24, 2, 13), (5, 6, 64, 64, 1, 14),
+    (3, 4, 10, 10, 3, 15)])
+def test_random_state_truncating_parity(R, C, chi, init_chi, steps, seed):
+    """Symmetry-free seeded start state: every truncation has a unique
+    result, so all observables, fidelities and per-update f must agree."""
+    sites, centre = workloads.random_mps(R, C, init_chi, seed)
+    cfg = mpsim.make_config(R, C, chi, theta0=0.0)
+    sim = mpsim.Simulation(cfg)
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(Grid(R, C), chi, sites, centre, J, H, DT)
+    a, b = sim.measure(), ora.measure()
+    assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
+    for _ in range(steps):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        print(R, C, chi, "z err", abs(a["z"] - b["z"]), "z2 err", abs(a["z2"] - b["z2"]),
+              "logF err", abs(a["log_fidelity"] - b["log_fidelity"]), "logF", b["log_fidelity"])
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL
+    assert sim.bond_dims() == ora.bond_dims()
