@@ -6,9 +6,14 @@ transverse-field Ising grid (two half-row blocks of 4 qubits per row: d = 16,
 One step = one whole Trotter step of the hot path: every two-site update of
 the block-pair schedule (contraction with the gate, Gram matrix, top-chi
 eigenspace, truncation, fidelity), the single-site layer, and one
-measurement of <Z_tot>, <Z_tot^2> and F_MPS. The state starts as the paper's
-product state (theta0 = pi/18, J = -1, h = 2, dt = 0.25); `--warmup` steps
-bring the bonds to their saturated sizes before the timed steps.
+measurement of <Z_tot>, <Z_tot^2> and F_MPS, with the paper's couplings
+(J = -1, h = 2, dt = 0.25).
+
+Start state (`--start`): `random` (default) is a seeded random MPS in mixed
+canonical form at the saturated bond dimensions of the workload
+([1, 16, 256, 1024 x 7, 256, 16, 1]), so every timed step has steady-state
+shapes; `product` is the paper's product state (theta0 = pi/18), whose first
+steps are cheaper while the bonds grow (use --warmup to skip them).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -119,7 +124,11 @@ def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--start", default="random", choices=["random", "product"])
+    ap.add_argument("--seed", type=int, default=1234)
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="counter sample: a 1 GiB copy, then one bulk two-site update")
     ap.add_argument("--rows", type=int, default=6)
     ap.add_argument("--cols", type=int, default=8)
     ap.add_argument("--chi", type=int, default=1024)
@@ -144,14 +153,43 @@ def main() -> int:
     cfg = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
                             precision=args.precision)
     sim = mpsim.Simulation(cfg)
+    if args.start == "random" or args.pmc_sample:
+        from paper_2511_23438_amd import workloads
+        centre = args.rows - 1
+        sites, centre = workloads.random_mps(args.rows, args.cols, args.chi, args.seed,
+                                             centre=centre)
+        sim.set_state(sites, centre)
+        del sites
+        log("random start state loaded, bonds %s" % sim.bond_dims())
+    if args.pmc_sample:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy of 1 GiB done")
+        t0 = time.perf_counter()
+        sim.apply_two_site(args.rows - 1, 0, 1)
+        sim.sync()
+        log("bulk update done in %.2fs" % (time.perf_counter() - t0))
+        print(json.dumps({"pmc_sample": True, "workload": "tfim_%dx%d_chi%d" % (
+            args.rows, args.cols, args.chi)}), flush=True)
+        return 0
     for w in range(args.warmup):
         t0 = time.perf_counter()
         sim.step(1)
         sim.sync()
         log("warmup step %d: %.2fs bonds %s" % (w + 1, time.perf_counter() - t0, sim.bond_dims()))
 
+    t_start = [time.perf_counter()]
+
+    def progress(step, upd, n):
+        if upd % 6 == 0 or upd == n:
+            log("  step %d: update %d/%d enqueued, %.1fs" % (step + 1, upd, n,
+                                                           time.perf_counter() - t_start[0]))
+    sim.set_progress(progress)
     sim.profile(args.prof)
     torch.cuda.synchronize()
+    t_start[0] = time.perf_counter()
     t0 = time.perf_counter()
     for k in range(args.steps):
         sim.step(1)
@@ -191,7 +229,9 @@ def main() -> int:
                    "d": 2 ** ((args.cols + 1) // 2), "sites": 2 * args.rows, "chi": args.chi,
                    "precision": args.precision, "theta0": args.theta0, "J": -1.0, "h": 2.0,
                    "dt": 0.25, "trotter_order": 1, "schedule": "block-pair",
-                   "start": "product state + %d warmup steps" % args.warmup},
+                   "start": ("seeded random MPS at saturated bonds (seed %d)" % args.seed
+                             if args.start == "random" else "product state")
+                            + (" + %d warmup steps" % args.warmup if args.warmup else "")},
         "roofline": roof,
         "observables": {"z": obs["z"], "z2": obs["z2"], "fidelity": obs["fidelity"],
                         "norm": obs["norm"]},

@@ -55,7 +55,7 @@ typedef enum {
 typedef enum {
   MPS_FP64 = 0,            /* all contractions and the truncation in float64 */
   MPS_C64_FP32ACC = 1,     /* complex64 contractions, FP32 accumulation, FP64 truncation */
-  MPS_BF16X3_FP32ACC = 2   /* bf16 hi/lo split (3 products), FP32 accumulation, FP64 truncation */
+  MPS_BF16X3_FP32ACC = 2   /* three-term bf16 split (hi+mid+lo, 6 products), FP32 accumulation, FP64 truncation */
 } mps_precision;
 
 /* Optional device allocator (e.g. a framework's caching allocator). All
@@ -183,6 +183,12 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len);
  * device overlaps independent instances (each handle keeps its own stream).
  * Results equal applying the steps to each handle alone. */
 mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t nsteps);
+
+/* Optional progress callback: called on the host after each two-site update
+ * of mps_apply_trotter_step has been enqueued, with the index of the update
+ * within the step and the number of updates per step. NULL removes it. */
+typedef void (*mps_progress_fn)(void* ctx, int32_t step, int32_t update, int32_t updates_per_step);
+mps_status mps_set_progress(mps_handle h, mps_progress_fn fn, void* ctx);
 
 /* Synchronise the handle's stream and report any pending device error. */
 mps_status mps_sync(mps_handle h);

@@ -15,6 +15,9 @@ struct ZOp {
 };
 
 enum { EPI_STORE = 0, EPI_THETA = 1 };
+// arithmetic of the product: float64, complex64 with FP32 accumulation, or a
+// bf16 hi/lo split (hi*hi + hi*lo + lo*hi) with FP32 accumulation
+enum { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
 
 struct ZGemm {
   int M, N, K, batch;
@@ -31,6 +34,11 @@ struct ZGemm {
   const cplx* phase;
   int phase_trans, d1, d2, b2, swap;
   int tag;          // launch class for the profiler (PROF_GRAM, PROF_THETA or 0)
+  int prec;         // GEMM_F64 (default), GEMM_F32 or GEMM_BF16X3
+  // optional second K segment: for k >= kcat the operands are A2 (i, k - kcat)
+  // and B2 (k - kcat, j); A2/B2 share the trans and conj flags of A/B
+  int kcat;
+  ZOp A2, B2;
 };
 
 // C = alpha*op(A)*op(B) + beta*C (or the theta epilogue). `partial` is a

@@ -28,6 +28,31 @@ struct ZGemmDev {
   cplx* partial;
 };
 
+// element (i, k) of op(A) before conjugation, with the optional second K segment
+template <int TA>
+__device__ inline cplx elem_a(const ZGemm& g, const cplx* A, long gi, long gk) {
+  const cplx* P = A;
+  long ld = g.A.ld;
+  if (g.kcat && gk >= g.kcat) {
+    P = g.A2.p;
+    ld = g.A2.ld;
+    gk -= g.kcat;
+  }
+  return TA == 0 ? P[gi * ld + gk] : P[gk * ld + gi];
+}
+
+template <int TB>
+__device__ inline cplx elem_b(const ZGemm& g, const cplx* B, long gk, long gj) {
+  const cplx* P = B;
+  long ld = g.B.ld;
+  if (g.kcat && gk >= g.kcat) {
+    P = g.B2.p;
+    ld = g.B2.ld;
+    gk -= g.kcat;
+  }
+  return TB == 0 ? P[gk * ld + gj] : P[gj * ld + gk];
+}
+
 template <int TA>
 __device__ inline void load_a(const ZGemm& g, const cplx* A, int m0, long k0, long kend,
                               cplx r[4]) {
@@ -38,7 +63,7 @@ __device__ inline void load_a(const ZGemm& g, const cplx* A, int m0, long k0, lo
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       long gk = k0 + kk + u;
-      r[u] = (gi < g.M && gk < kend) ? A[gi * g.A.ld + gk] : make_double2(0, 0);
+      r[u] = (gi < g.M && gk < kend) ? elem_a<TA>(g, A, gi, gk) : make_double2(0, 0);
     }
   } else {        // (i,k) at A[k*ld + i]: 4 consecutive i per thread
     int k = t >> 4, ii = (t & 15) * 4;
@@ -46,7 +71,7 @@ __device__ inline void load_a(const ZGemm& g, const cplx* A, int m0, long k0, lo
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       long gi = m0 + ii + u;
-      r[u] = (gi < g.M && gk < kend) ? A[gk * g.A.ld + gi] : make_double2(0, 0);
+      r[u] = (gi < g.M && gk < kend) ? elem_a<TA>(g, A, gi, gk) : make_double2(0, 0);
     }
   }
 }
@@ -61,7 +86,7 @@ __device__ inline void load_b(const ZGemm& g, const cplx* B, int n0, long k0, lo
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       long gj = n0 + jj + u;
-      r[u] = (gj < g.N && gk < kend) ? B[gk * g.B.ld + gj] : make_double2(0, 0);
+      r[u] = (gj < g.N && gk < kend) ? elem_b<TB>(g, B, gk, gj) : make_double2(0, 0);
     }
   } else {        // (k,j) at B[j*ld + k]: 4 consecutive k
     int j = t >> 2, kk = (t & 3) * 4;
@@ -69,7 +94,7 @@ __device__ inline void load_b(const ZGemm& g, const cplx* B, int n0, long k0, lo
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       long gk = k0 + kk + u;
-      r[u] = (gj < g.N && gk < kend) ? B[gj * g.B.ld + gk] : make_double2(0, 0);
+      r[u] = (gj < g.N && gk < kend) ? elem_b<TB>(g, B, gk, gj) : make_double2(0, 0);
     }
   }
 }
@@ -102,6 +127,33 @@ __device__ inline void store_b(double (*Bs)[BK][BN], const cplx r[4], int conj) 
 #pragma unroll
     for (int u = 0; u < 4; ++u) { Bs[0][kk + u][j] = r[u].x; Bs[1][kk + u][j] = sg * r[u].y; }
   }
+}
+
+// Store one result element: split-K partial, theta epilogue (phase, SWAP
+// layout) or alpha*val + beta*C.
+__device__ inline void store_out(const ZGemmDev& gd, int bz, int bat, long row, long col, cplx val) {
+  const ZGemm& g = gd.g;
+  if (row >= g.M || col >= g.N) return;
+  if (gd.ksplit > 1) {
+    gd.partial[((long)bz * g.M + row) * g.N + col] = val;
+    return;
+  }
+  cplx* C = g.C + (long)bat * g.strideC;
+  if (g.epi == EPI_THETA) {
+    const long al = row / g.d1, s1 = row % g.d1;
+    const long s2 = col / g.b2, gg = col % g.b2;
+    if (g.phase) {
+      cplx ph = g.phase_trans ? g.phase[s2 * g.d1 + s1] : g.phase[s1 * g.d2 + s2];
+      val = cmul(val, ph);
+    }
+    if (g.swap) C[(al * g.d2 + s2) * ((long)g.d1 * g.b2) + s1 * g.b2 + gg] = val;
+    else C[row * g.ldc + col] = val;
+    return;
+  }
+  const long idx = g.transC ? col * g.ldc + row : row * g.ldc + col;
+  cplx out = cmul(g.alpha, val);
+  if (g.beta.x != 0.0 || g.beta.y != 0.0) out = cadd(out, cmul(g.beta, C[idx]));
+  C[idx] = out;
 }
 
 template <int TA, int TB>
@@ -171,38 +223,277 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
     }
   }
 
-  // epilogue
+  // epilogue (f64 result layout: register v of lane l is row 4v + l/16)
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const long row = m0 + wr + a * 16 + 4 * v + (l >> 4);
-        const long col = n0 + wc + b * 16 + (l & 15);
-        if (row >= g.M || col >= g.N) continue;
-        cplx val = make_double2(cr[a][b][v], ci[a][b][v]);
-        if (gd.ksplit > 1) {
-          gd.partial[((long)bz * g.M + row) * g.N + col] = val;
-          continue;
-        }
-        cplx* C = g.C + (long)bat * g.strideC;
-        if (g.epi == EPI_THETA) {
-          const long al = row / g.d1, s1 = row % g.d1;
-          const long s2 = col / g.b2, gg = col % g.b2;
-          if (g.phase) {
-            cplx ph = g.phase_trans ? g.phase[s2 * g.d1 + s1] : g.phase[s1 * g.d2 + s2];
-            val = cmul(val, ph);
-          }
-          if (g.swap) C[(al * g.d2 + s2) * ((long)g.d1 * g.b2) + s1 * g.b2 + gg] = val;
-          else C[row * g.ldc + col] = val;
-          continue;
-        }
-        const long idx = g.transC ? col * g.ldc + row : row * g.ldc + col;
-        cplx out = cmul(g.alpha, val);
-        if (g.beta.x != 0.0 || g.beta.y != 0.0) out = cadd(out, cmul(g.beta, C[idx]));
-        C[idx] = out;
+      for (int v = 0; v < 4; ++v)
+        store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + wc + b * 16 + (l & 15),
+                  make_double2(cr[a][b][v], ci[a][b][v]));
+}
+
+
+// ---------------------------------------------------------------------------
+// Reduced-precision products. Operands are read as complex128 from HBM and
+// rounded when staged into LDS.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+template <int TA>
+__device__ inline void store_a_f32(float (*As)[BK][BM], const cplx r[4], int conj) {
+  const int t = threadIdx.x;
+  const float sg = conj ? -1.f : 1.f;
+  if (TA == 0) {
+    const int i = t >> 2, kk = (t & 3) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { As[0][kk + u][i] = (float)r[u].x; As[1][kk + u][i] = sg * (float)r[u].y; }
+  } else {
+    const int k = t >> 4, ii = (t & 15) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { As[0][k][ii + u] = (float)r[u].x; As[1][k][ii + u] = sg * (float)r[u].y; }
+  }
+}
+
+template <int TB>
+__device__ inline void store_b_f32(float (*Bs)[BK][BN], const cplx r[4], int conj) {
+  const int t = threadIdx.x;
+  const float sg = conj ? -1.f : 1.f;
+  if (TB == 0) {
+    const int k = t >> 4, jj = (t & 15) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { Bs[0][k][jj + u] = (float)r[u].x; Bs[1][k][jj + u] = sg * (float)r[u].y; }
+  } else {
+    const int j = t >> 2, kk = (t & 3) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { Bs[0][kk + u][j] = (float)r[u].x; Bs[1][kk + u][j] = sg * (float)r[u].y; }
+  }
+}
+
+// complex64 GEMM, FP32 accumulation, v_mfma_f32_16x16x4f32
+// (result register v of lane l is row 4*(l/16) + v).
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void cgemm_f32_kernel(ZGemmDev gd) {
+  const ZGemm& g = gd.g;
+  __shared__ float As[2][BK][BM];
+  __shared__ float Bs[2][BK][BN];
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  if (g.lower_only && n0 >= m0 + BM) return;
+  if (g.upper_only && m0 >= n0 + BN) return;
+  const int bz = blockIdx.z;
+  const int bat = bz / gd.ksplit, ks = bz % gd.ksplit;
+  const cplx* A = g.A.p + (long)bat * g.A.stride;
+  const cplx* B = g.B.p + (long)bat * g.B.stride;
+  const long kbeg = (long)ks * gd.kchunk;
+  long kend = kbeg + gd.kchunk;
+  if (kend > g.K) kend = g.K;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (f4){0, 0, 0, 0};
+      ci[a][b] = (f4){0, 0, 0, 0};
+    }
+  cplx ra[4], rb[4];
+  if (kbeg < kend) {
+    load_a<TA>(g, A, m0, kbeg, kend, ra);
+    load_b<TB>(g, B, n0, kbeg, kend, rb);
+  }
+  for (long k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    store_a_f32<TA>(As, ra, g.A.conj);
+    store_b_f32<TB>(Bs, rb, g.B.conj);
+    __syncthreads();
+    if (k0 + BK < kend) {
+      load_a<TA>(g, A, m0, k0 + BK, kend, ra);
+      load_b<TB>(g, B, n0, k0 + BK, kend, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (l >> 4);
+      float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = As[0][kr][wr + a * 16 + (l & 15)];
+        ai[a] = As[1][kr][wr + a * 16 + (l & 15)];
       }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        br[b] = Bs[0][kr][wc + b * 16 + (l & 15)];
+        bi[b] = Bs[1][kr][wc + b * 16 + (l & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[a], br[b], cr[a][b], 0, 0, 0);
+          cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[a], bi[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[a], bi[b], ci[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[a], br[b], ci[a][b], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * (l >> 4) + v, n0 + wc + b * 16 + (l & 15),
+                  make_double2((double)cr[a][b][v], (double)ci[a][b][v]));
+}
+
+// Three-term bf16 split: x = hi + mid + lo with hi = bf16(x),
+// mid = bf16(x - hi), lo = bf16(x - hi - mid) (24 significant bits, the
+// precision of FP32). A product keeps the six partial products of relative
+// order >= 2^-16 (hh, hm, mh, hl, lh, mm), accumulated in FP32 on
+// v_mfma_f32_16x16x32_bf16. LDS planes per operand: re (h, m, l), im (h, m,
+// l), and for B also -im; K = 32 per stage, k contiguous so that one lane
+// reads its 8 consecutive k values at once.
+#define BK2 32
+#define KP (BK2 + 8)
+
+__device__ inline void split3_bf16(float x, __bf16& h, __bf16& m, __bf16& lo) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;
+  m = (__bf16)r1;
+  lo = (__bf16)(r1 - (float)m);
+}
+
+template <int TA>
+__device__ inline void stage_a_bf(__bf16 (*As)[BM][KP], const cplx r[4], int kofs, int conj) {
+  const int t = threadIdx.x;
+  const float sg = conj ? -1.f : 1.f;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int i, k;
+    if (TA == 0) { i = t >> 2; k = (t & 3) * 4 + u; }
+    else { k = t >> 4; i = (t & 15) * 4 + u; }
+    __bf16 h, m, lo;
+    split3_bf16((float)r[u].x, h, m, lo);
+    As[0][i][kofs + k] = h; As[1][i][kofs + k] = m; As[2][i][kofs + k] = lo;
+    split3_bf16(sg * (float)r[u].y, h, m, lo);
+    As[3][i][kofs + k] = h; As[4][i][kofs + k] = m; As[5][i][kofs + k] = lo;
+  }
+}
+
+template <int TB>
+__device__ inline void stage_b_bf(__bf16 (*Bs)[BN][KP], const cplx r[4], int kofs, int conj) {
+  const int t = threadIdx.x;
+  const float sg = conj ? -1.f : 1.f;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int j, k;
+    if (TB == 0) { k = t >> 4; j = (t & 15) * 4 + u; }
+    else { j = t >> 2; k = (t & 3) * 4 + u; }
+    __bf16 h, m, lo;
+    split3_bf16((float)r[u].x, h, m, lo);
+    Bs[0][j][kofs + k] = h; Bs[1][j][kofs + k] = m; Bs[2][j][kofs + k] = lo;
+    const float im = sg * (float)r[u].y;
+    split3_bf16(im, h, m, lo);
+    Bs[3][j][kofs + k] = h; Bs[4][j][kofs + k] = m; Bs[5][j][kofs + k] = lo;
+    Bs[6][j][kofs + k] = -h; Bs[7][j][kofs + k] = -m; Bs[8][j][kofs + k] = -lo;
+  }
+}
+
+__device__ inline bf8 ld8(const __bf16* p) {
+  bf8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = p[e];
+  return v;
+}
+
+// acc += x * y for split operands x = (xh, xm, xl), y = (yh, ym, yl)
+__device__ inline f4 mfma_split3(const bf8* x, const bf8* y, f4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[1], acc, 0, 0, 0);
+  return acc;
+}
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
+  const ZGemm& g = gd.g;
+  __shared__ __bf16 As[6][BM][KP];
+  __shared__ __bf16 Bs[9][BN][KP];
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  if (g.lower_only && n0 >= m0 + BM) return;
+  if (g.upper_only && m0 >= n0 + BN) return;
+  const int bz = blockIdx.z;
+  const int bat = bz / gd.ksplit, ks = bz % gd.ksplit;
+  const cplx* A = g.A.p + (long)bat * g.A.stride;
+  const cplx* B = g.B.p + (long)bat * g.B.stride;
+  const long kbeg = (long)ks * gd.kchunk;
+  long kend = kbeg + gd.kchunk;
+  if (kend > g.K) kend = g.K;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = (f4){0, 0, 0, 0};
+      ci[a][b] = (f4){0, 0, 0, 0};
+    }
+  for (long k0 = kbeg; k0 < kend; k0 += BK2) {
+    cplx ra[4], rb[4];
+    __syncthreads();
+    load_a<TA>(g, A, m0, k0, kend, ra);
+    load_b<TB>(g, B, n0, k0, kend, rb);
+    stage_a_bf<TA>(As, ra, 0, g.A.conj);
+    stage_b_bf<TB>(Bs, rb, 0, g.B.conj);
+    load_a<TA>(g, A, m0, k0 + BK, kend, ra);
+    load_b<TB>(g, B, n0, k0 + BK, kend, rb);
+    stage_a_bf<TA>(As, ra, BK, g.A.conj);
+    stage_b_bf<TB>(Bs, rb, BK, g.B.conj);
+    __syncthreads();
+    const int kq = 8 * (l >> 4);
+    bf8 are[2][3], aim[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = wr + a * 16 + (l & 15);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        are[a][p] = ld8(&As[p][i][kq]);
+        aim[a][p] = ld8(&As[3 + p][i][kq]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = wc + b * 16 + (l & 15);
+      bf8 bre[3], bim[3], bnim[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        bre[p] = ld8(&Bs[p][j][kq]);
+        bim[p] = ld8(&Bs[3 + p][j][kq]);
+        bnim[p] = ld8(&Bs[6 + p][j][kq]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        cr[a][b] = mfma_split3(are[a], bre, cr[a][b]);
+        cr[a][b] = mfma_split3(aim[a], bnim, cr[a][b]);
+        ci[a][b] = mfma_split3(are[a], bim, ci[a][b]);
+        ci[a][b] = mfma_split3(aim[a], bre, ci[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * (l >> 4) + v, n0 + wc + b * 16 + (l & 15),
+                  make_double2((double)cr[a][b][v], (double)ci[a][b][v]));
 }
 
 // Sum the split-K partials and apply the store epilogue.
@@ -233,6 +524,9 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     std::swap(g.A, g.B);
     g.A.trans ^= 1;
     g.B.trans ^= 1;
+    std::swap(g.A2, g.B2);
+    g.A2.trans ^= 1;
+    g.B2.trans ^= 1;
     std::swap(g.M, g.N);
     g.transC = 0;
     std::swap(g.lower_only, g.upper_only);
@@ -252,13 +546,13 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(256), 0, s, z);
     return;
   }
-  if (partial && g.epi == EPI_STORE && !g.lower_only && !g.upper_only && tiles < 128 &&
-      g.K >= 1024) {
+  if (partial && g.epi == EPI_STORE && !g.lower_only && !g.upper_only && !g.kcat &&
+      tiles < 128 && g.K >= 1024) {
     int ks = (int)std::min<long>(g.K / 256, (256 + tiles - 1) / tiles);
     while (ks > 1 && (long)ks * g.batch * g.M * g.N > partial_elems) --ks;
     if (ks > 1) {
       gd.ksplit = ks;
-      gd.kchunk = ((g.K + ks - 1) / ks + BK - 1) / BK * BK;
+      gd.kchunk = ((g.K + ks - 1) / ks + BK2 - 1) / BK2 * BK2;
       gd.ksplit = (int)((g.K + gd.kchunk - 1) / gd.kchunk);
     }
   }
@@ -268,10 +562,17 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
   double flops = 8.0 * g.M * (double)g.N * g.K * g.batch;
   if (g.lower_only || g.upper_only) flops = 8.0 * g.M * (g.M + 1.0) * 0.5 * g.K * g.batch;
   if (prof) prof->begin(pk, s);
-  if (ta == 0 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(256), 0, s, gd);
-  else if (ta == 0 && tb == 1) hipLaunchKernelGGL((zgemm_kernel<0, 1>), grid, dim3(256), 0, s, gd);
-  else if (ta == 1 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<1, 0>), grid, dim3(256), 0, s, gd);
-  else hipLaunchKernelGGL((zgemm_kernel<1, 1>), grid, dim3(256), 0, s, gd);
+#define MPS_GEMM_DISPATCH(KER)                                                              \
+  do {                                                                                      \
+    if (ta == 0 && tb == 0) hipLaunchKernelGGL((KER<0, 0>), grid, dim3(256), 0, s, gd);     \
+    else if (ta == 0 && tb == 1) hipLaunchKernelGGL((KER<0, 1>), grid, dim3(256), 0, s, gd); \
+    else if (ta == 1 && tb == 0) hipLaunchKernelGGL((KER<1, 0>), grid, dim3(256), 0, s, gd); \
+    else hipLaunchKernelGGL((KER<1, 1>), grid, dim3(256), 0, s, gd);                         \
+  } while (0)
+  if (g.prec == GEMM_F32) MPS_GEMM_DISPATCH(cgemm_f32_kernel);
+  else if (g.prec == GEMM_BF16X3) MPS_GEMM_DISPATCH(cgemm_bf16x3_kernel);
+  else MPS_GEMM_DISPATCH(zgemm_kernel);
+#undef MPS_GEMM_DISPATCH
   if (gd.ksplit > 1) {
     long total = (long)g.M * g.N;
     int blocks = (int)std::min<long>((total + 255) / 256, 4096);

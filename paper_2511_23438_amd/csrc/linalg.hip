@@ -50,25 +50,38 @@ static ZOp strided_op(const cplx* base, long rs, long cs, int conj = 0) {
 }
 
 // ---------------------------------------------------------------------------
-// Tridiagonalisation (lower), panels of TRD_NB columns, two launches per column:
-//   k_trd_col  : finish the previous column of the panel (scale its reflector,
-//                add alpha*v to its W column), apply the panel's earlier
-//                reflectors to column c, and reduce |x|^2, W^H x, V^H x;
-//   k_trd_hemv : reflector of column c, then y = A22 v on the lower-triangle
-//                tiles of the trailing matrix; the last workgroup to
-//                contribute to a 64-row block finalises that block of the new
-//                W column, and the last block finalised computes alpha.
-// scal: [0] beta [1,2] tau [3,4] scale [5,6] alpha of the latest column.
+// Tridiagonalisation (lower), panels of TRD_NB columns. Per column c:
+//   k_trd_col  : finish the previous column of the panel (alpha from its
+//                partial dot products, scale its reflector, add alpha*v to
+//                its W column), apply the panel's earlier reflectors to
+//                column c, and partial sums of |x|^2, W^H x, V^H x;
+//   k_trd_hemv : forms the reflector from those partials (every workgroup,
+//                identically), then y = A22 v on the lower-triangle tiles of
+//                the trailing matrix;
+//   k_trd_w    : sums the tile partials of each row, subtracts the panel
+//                corrections, scales by tau into the new W column, and
+//                partial sums of y^H v.
+// Hand-offs between workgroups happen only at kernel boundaries (device-scope
+// fences cost a write-back of the per-XCD L2 on this part).
+// scal: [0] beta [1,2] tau [3,4] scale of the latest column.
 #define TP (2 * TRD_NB + 1)
 
+__device__ inline cplx trd_alpha(const double* scal, const cplx* dpart, int ndp) {
+  cplx ds = make_double2(0.0, 0.0);
+  for (int b = 0; b < ndp; ++b) ds = cadd(ds, dpart[b]);
+  return cscale(cmul(make_double2(scal[1], scal[2]), ds), -0.5);
+}
+
 __global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, cplx* W, long ldw, int i0,
-                                                 int j, int c, const double* scal, cplx* tpart,
-                                                 cplx* tsum, int* cnt) {
+                                                 int j, int c, const double* scal, const cplx* dpart,
+                                                 int ndp, cplx* tpart) {
   __shared__ cplx wrow[TRD_NB], vrow[TRD_NB];
-  __shared__ cplx sh[4 * TP];
-  __shared__ int last;
+  __shared__ cplx sh[4 * 64];
+  __shared__ cplx alpha_s;
   const int t = threadIdx.x;
-  const cplx alpha = make_double2(scal[5], scal[6]);
+  if (t == 0 && j > 0) alpha_s = trd_alpha(scal, dpart, ndp);
+  __syncthreads();
+  const cplx alpha = (j > 0) ? alpha_s : make_double2(0.0, 0.0);
   const cplx scp = make_double2(scal[3], scal[4]);
   if (t < j) {
     cplx wv = W[(long)t * ldw + c];
@@ -103,38 +116,54 @@ __global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, cplx*
   const bool act = (r < n) && (r >= c + 2);
   const int count = 1 + 2 * j;
   const int lane = t & 63, wv = t >> 6;
-  // value k: 0 -> |x|^2, 1..j -> conj(W[r, jj]) x, j+1..2j -> conj(V[r, jj]) x
-  for (int kk = 0; kk < count; ++kk) {
-    cplx v = make_double2(0.0, 0.0);
-    if (act) {
-      if (kk == 0) {
-        v = make_double2(cabs2(a), 0.0);
-      } else {
-        const int jj = (kk <= j) ? kk - 1 : kk - 1 - j;
-        if (kk <= j) v = cmulc((jj == j - 1) ? wfix : W[(long)jj * ldw + r], a);
-        else v = cmulc((jj == j - 1) ? vprev : A[(long)(i0 + jj) * lda + r], a);
+  // values k < count: 0 -> |x|^2, 1..j -> conj(W[r, jj]) x, j+1..2j ->
+  // conj(V[r, jj]) x; reduced over the wave 16 at a time by a butterfly that
+  // halves the number of values held per lane at each exchange (16 -> 1),
+  // then two plain exchanges.
+  for (int g0 = 0; g0 < count; g0 += 16) {
+    cplx vals[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int kk = g0 + u;
+      cplx v = make_double2(0.0, 0.0);
+      if (act && kk < count) {
+        if (kk == 0) {
+          v = make_double2(cabs2(a), 0.0);
+        } else {
+          const int jj = (kk <= j) ? kk - 1 : kk - 1 - j;
+          if (kk <= j) v = cmulc((jj == j - 1) ? wfix : W[(long)jj * ldw + r], a);
+          else v = cmulc((jj == j - 1) ? vprev : A[(long)(i0 + jj) * lda + r], a);
+        }
+      }
+      vals[u] = v;
+    }
+#pragma unroll
+    for (int half = 8, m = 32; half >= 1; half >>= 1, m >>= 1) {
+      const bool upper = (lane & m) != 0;
+#pragma unroll
+      for (int q2 = 0; q2 < half; ++q2) {
+        const cplx keep = upper ? vals[q2 + half] : vals[q2];
+        const cplx send = upper ? vals[q2] : vals[q2 + half];
+        cplx got;
+        got.x = __shfl_xor(send.x, m, 64);
+        got.y = __shfl_xor(send.y, m, 64);
+        vals[q2] = cadd(keep, got);
       }
     }
-    v = wave_csum(v);
-    if (lane == 0) sh[wv * TP + kk] = v;
-  }
-  __syncthreads();
-  for (int kk = t; kk < count; kk += blockDim.x)
-    tpart[(long)blockIdx.x * TP + kk] = cadd(cadd(sh[kk], sh[TP + kk]), cadd(sh[2 * TP + kk], sh[3 * TP + kk]));
-  __threadfence();
-  if (t == 0) last = (atomicAdd(cnt, 1) == (int)gridDim.x - 1);
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    for (int k = t; k < count; k += blockDim.x) {
-      cplx acc = make_double2(0.0, 0.0);
-      for (int b = 0; b < (int)gridDim.x; ++b) acc = cadd(acc, tpart[(long)b * TP + k]);
-      // layout of tsum: [0] |x|^2, [1 + jj] W^H x, [1 + TRD_NB + jj] V^H x
-      const int dst = (k == 0) ? 0 : (k <= j ? k : 1 + TRD_NB + (k - 1 - j));
-      tsum[dst] = acc;
+    cplx z = vals[0];
+    z.x += __shfl_xor(z.x, 2, 64);
+    z.y += __shfl_xor(z.y, 2, 64);
+    z.x += __shfl_xor(z.x, 1, 64);
+    z.y += __shfl_xor(z.y, 1, 64);
+    if ((lane & 3) == 0) {
+      const int vid = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+                      ((lane >> 2) & 1);
+      sh[wv * 64 + g0 + vid] = z;
     }
-    if (t == 0) *cnt = 0;
   }
+  __syncthreads();
+  if (t < count)
+    tpart[(long)blockIdx.x * TP + t] = cadd(cadd(sh[t], sh[64 + t]), cadd(sh[128 + t], sh[192 + t]));
 }
 
 __device__ inline cplx trd_v(const cplx* A, long lda, int n, int c, long r, cplx sc) {
@@ -143,120 +172,156 @@ __device__ inline cplx trd_v(const cplx* A, long lda, int n, int c, long r, cplx
   return cmul(A[(long)c * lda + r], sc);
 }
 
-__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, cplx* W, long ldw,
-                                                  int i0, int j, int c, const cplx* tsum, cplx* P,
-                                                  int nt, int* cnt, cplx* dpart, double* scal,
-                                                  double* d, double* e, cplx* tau) {
+// y = A22 v over the lower-triangle tiles (64 x 64) of the trailing matrix;
+// tile (I, J) writes A_IJ v_J to P[I][J] and, off the diagonal, A_IJ^H v_I to
+// P[J][I].
+__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, int c,
+                                                     const cplx* tpart, int nparts, double* scal,
+                                                     double* d, double* e, cplx* tau, cplx* P, int nt) {
   __shared__ cplx vI[64], vJ[64];
   __shared__ cplx red[4][64];
-  __shared__ cplx t1[TRD_NB], t2[TRD_NB];
-  __shared__ int fin[2];
-  __shared__ double dsh[4];
+  __shared__ cplx sc_s;
   const int t = threadIdx.x;
+  if (t == 0) {
+    // reflector of column c from |x|^2 (partials of the column kernel)
+    double xn = 0.0;
+    for (int b = 0; b < nparts; ++b) xn += tpart[(long)b * TP].x;
+    double beta;
+    cplx tauv, scl;
+    reflector(A[(long)c * lda + c + 1], xn, beta, tauv, scl);
+    sc_s = scl;
+    if (blockIdx.x == 0) {
+      scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = scl.x; scal[4] = scl.y;
+      tau[c] = tauv;
+      e[c] = beta;
+      d[c] = A[(long)c * lda + c].x;
+    }
+  }
+  __syncthreads();
   const long k = blockIdx.x;
   long I = (long)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
   while (I * (I + 1) / 2 > k) --I;
   while ((I + 1) * (I + 2) / 2 <= k) ++I;
   const long J = k - I * (I + 1) / 2;
   const int o = c + 1;
-  double beta;
-  cplx tauv, sc;
-  reflector(A[(long)c * lda + o], tsum[0].x, beta, tauv, sc);
-  if (blockIdx.x == 0 && t == 0) {
-    scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = sc.x; scal[4] = sc.y;
-    tau[c] = tauv;
-    e[c] = beta;
-    d[c] = A[(long)c * lda + c].x;
-  }
+  const cplx sc = sc_s;
   if (t < 64) vI[t] = trd_v(A, lda, n, c, o + I * 64 + t, sc);
   else if (t < 128) vJ[t - 64] = trd_v(A, lda, n, c, o + J * 64 + (t - 64), sc);
   __syncthreads();
   const int rr = t & 63, cg = t >> 6;
   const long row = o + I * 64 + rr;
   cplx y = make_double2(0.0, 0.0);
-  for (int cc = 0; cc < 16; ++cc) {
-    const int cl = cg * 16 + cc;
-    const long col = o + J * 64 + cl;
-    cplx a = make_double2(0.0, 0.0);
-    const bool in = row < n && col < n;
-    if (I == J) {
-      if (in) {
+  if (I == J) {
+    for (int cc = 0; cc < 16; ++cc) {
+      const int cl = cg * 16 + cc;
+      const long col = o + J * 64 + cl;
+      cplx a = make_double2(0.0, 0.0);
+      if (row < n && col < n) {
         if (cl < rr) a = A[col * lda + row];
         else if (cl > rr) a = cconj(A[row * lda + col]);
         else a = make_double2(A[col * lda + row].x, 0.0);
       }
       y = cadd(y, cmul(a, vJ[cl]));
-    } else {
-      if (in) a = A[col * lda + row];
-      y = cadd(y, cmul(a, vJ[cl]));
-      cplx z = wave_csum(cmulc(a, vI[rr]));
-      if (rr == 0) P[(J * nt + I) * 64 + cl] = z;
+    }
+  } else {
+    const cplx vi = vI[rr];
+#pragma unroll
+    for (int g8 = 0; g8 < 2; ++g8) {
+      cplx av[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const long col = o + J * 64 + cg * 16 + g8 * 8 + cc;
+        av[cc] = (row < n && col < n) ? A[col * lda + row] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        y = cadd(y, cmul(av[cc], vJ[cg * 16 + g8 * 8 + cc]));
+        av[cc] = cmulc(av[cc], vi);
+      }
+      // column sums over the 64 lanes: butterfly halving the values held per
+      // lane (8 -> 1), then three plain exchanges
+#pragma unroll
+      for (int half = 4, m = 32; half >= 1; half >>= 1, m >>= 1) {
+        const bool upper = (rr & m) != 0;
+#pragma unroll
+        for (int q2 = 0; q2 < half; ++q2) {
+          const cplx keep = upper ? av[q2 + half] : av[q2];
+          const cplx send = upper ? av[q2] : av[q2 + half];
+          cplx got;
+          got.x = __shfl_xor(send.x, m, 64);
+          got.y = __shfl_xor(send.y, m, 64);
+          av[q2] = cadd(keep, got);
+        }
+      }
+      cplx z = av[0];
+#pragma unroll
+      for (int m = 4; m >= 1; m >>= 1) {
+        z.x += __shfl_xor(z.x, m, 64);
+        z.y += __shfl_xor(z.y, m, 64);
+      }
+      // lane rr holds the sum for column b3 + 2 b4 + 4 b5 of this group
+      if ((rr & 7) == 0) {
+        const int colid = ((rr >> 5) & 1) * 4 + ((rr >> 4) & 1) * 2 + ((rr >> 3) & 1);
+        P[(J * nt + I) * 64 + cg * 16 + g8 * 8 + colid] = z;
+      }
     }
   }
   red[cg][rr] = y;
   __syncthreads();
   if (t < 64) P[(I * nt + J) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    fin[0] = (atomicAdd(&cnt[I], 1) == nt - 1) ? 1 : 0;
-    fin[1] = (I != J && atomicAdd(&cnt[J], 1) == nt - 1) ? 1 : 0;
+}
+
+// One workgroup per 64-row block: 4 threads per row sum every fourth tile
+// partial (neighbouring lanes read neighbouring rows), then the corrections.
+__global__ __launch_bounds__(256) void k_trd_w(int n, const cplx* A, long lda, cplx* W, long ldw, int i0,
+                                               int j, int c, const cplx* tpart, int nparts,
+                                               const cplx* P, int nt, const double* scal,
+                                               cplx* dpart) {
+  __shared__ cplx t1[TRD_NB], t2[TRD_NB];
+  __shared__ cplx part[4][64];
+  __shared__ double dsh[4];
+  const int t = threadIdx.x;
+  const int o = c + 1;
+  const cplx tauv = make_double2(scal[1], scal[2]);
+  const cplx sc = make_double2(scal[3], scal[4]);
+  if (t < 2 * j) {
+    // W^H x (t < j) and V^H x (t >= j) from the column partials
+    cplx acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < nparts; ++b) acc = cadd(acc, tpart[(long)b * TP + 1 + t]);
+    if (t < j) t1[t] = cadd(cconj(W[(long)t * ldw + o]), cmul(sc, acc));
+    else t2[t - j] = cadd(cconj(A[(long)(i0 + t - j) * lda + o]), cmul(sc, acc));
   }
+  const long I = blockIdx.x;
+  const int x = t & 63, q = t >> 6;
+  cplx acc = make_double2(0.0, 0.0);
+  for (long Jb = q; Jb < nt; Jb += 4) acc = cadd(acc, P[(I * nt + Jb) * 64 + x]);
+  part[q][x] = acc;
   __syncthreads();
-  if (!fin[0] && !fin[1]) return;
-  __threadfence();
-  if (t < j) {
-    t1[t] = cadd(cconj(W[(long)t * ldw + o]), cmul(sc, tsum[1 + t]));
-    t2[t] = cadd(cconj(A[(long)(i0 + t) * lda + o]), cmul(sc, tsum[1 + TRD_NB + t]));
+  cplx y = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+  const long r = o + I * 64 + x;
+  if (t < 64 && r < n) {
+    y = cadd(cadd(part[0][x], part[1][x]), cadd(part[2][x], part[3][x]));
+    for (int jj = 0; jj < j; ++jj)
+      y = csub(y, cadd(cmul(A[(long)(i0 + jj) * lda + r], t1[jj]), cmul(W[(long)jj * ldw + r], t2[jj])));
+    y = cmul(tauv, y);
+    W[(long)j * ldw + r] = y;
+    v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
   }
-  __syncthreads();
-  for (int f = 0; f < 2; ++f) {
-    if (!fin[f]) continue;
-    const long X = (f == 0) ? I : J;
-    double dre = 0.0, dim = 0.0;
-    if (t < 64) {
-      const long r = o + X * 64 + t;
-      if (r < n) {
-        cplx yy = make_double2(0.0, 0.0);
-        for (long Jb = 0; Jb < nt; ++Jb) yy = cadd(yy, P[(X * nt + Jb) * 64 + t]);
-        for (int jj = 0; jj < j; ++jj)
-          yy = csub(yy, cadd(cmul(A[(long)(i0 + jj) * lda + r], t1[jj]), cmul(W[(long)jj * ldw + r], t2[jj])));
-        yy = cmul(tauv, yy);
-        W[(long)j * ldw + r] = yy;
-        const cplx v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
-        const cplx dt = cmulc(yy, v);
-        dre = dt.x;
-        dim = dt.y;
-      }
-    }
-    dre = block_sum(dre, dsh);
-    dim = block_sum(dim, dsh);
-    if (t == 0) {
-      dpart[X] = make_double2(dre, dim);
-      cnt[X] = 0;
-    }
-    __threadfence();
-    __syncthreads();
-    if (t == 0) {
-      if (atomicAdd(&cnt[nt], 1) == nt - 1) {
-        __threadfence();
-        cplx ds = make_double2(0.0, 0.0);
-        for (int b = 0; b < nt; ++b) ds = cadd(ds, dpart[b]);
-        const cplx al = cscale(cmul(tauv, ds), -0.5);
-        scal[5] = al.x;
-        scal[6] = al.y;
-        cnt[nt] = 0;
-      }
-    }
-    __syncthreads();
-  }
+  const cplx dt = cmulc(y, v);
+  const double dre = block_sum(dt.x, dsh);
+  const double dim = block_sum(dt.y, dsh);
+  if (t == 0) dpart[blockIdx.x] = make_double2(dre, dim);
 }
 
 // Last column of a panel: scale its reflector, store the unit entry and add
 // alpha*v to its W column (rows c+1..n-1).
 __global__ __launch_bounds__(256) void k_trd_finish(int n, cplx* A, long lda, cplx* W, long ldw, int j,
-                                                    int c, const double* scal) {
-  const cplx alpha = make_double2(scal[5], scal[6]);
+                                                    int c, const double* scal, const cplx* dpart,
+                                                    int ndp) {
+  __shared__ cplx alpha_s;
+  if (threadIdx.x == 0) alpha_s = trd_alpha(scal, dpart, ndp);
+  __syncthreads();
+  const cplx alpha = alpha_s;
   const cplx sc = make_double2(scal[3], scal[4]);
   const long r = c + 1 + (long)blockIdx.x * 256 + threadIdx.x;
   if (r >= n) return;
@@ -273,41 +338,42 @@ __global__ void k_trd_last(int n, const cplx* A, long lda, double* d) {
 
 void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
   const long ldw = w.nmax;
+  int ndp = 0;
   for (int i0 = 0; i0 < n - 1; i0 += TRD_NB) {
     const int ib = std::min(TRD_NB, n - 1 - i0);
     for (int j = 0; j < ib; ++j) {
       const int c = i0 + j;
       const int nb1 = ceil_div(n - c, 256);
       hipLaunchKernelGGL(k_trd_col, dim3(nb1), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c,
-                         (const double*)w.scal, w.tpart, w.tsum, w.cnt + w.cnt_stride);
+                         (const double*)w.scal, (const cplx*)w.dpart, ndp, w.tpart);
       const int np = n - c - 1;
       const int nt = ceil_div(np, 64);
       const long ntiles = (long)nt * (nt + 1) / 2;
       if (w.prof) w.prof->begin(PROF_TRD_HEMV, s);
-      hipLaunchKernelGGL(k_trd_hemv, dim3((unsigned)ntiles), dim3(256), 0, s, n, (const cplx*)A, lda,
-                         w.W, ldw, i0, j, c, (const cplx*)w.tsum, w.P, nt, w.cnt, w.dpart, w.scal,
-                         w.d, w.e, w.tau);
+      hipLaunchKernelGGL(k_trd_hemv, dim3((unsigned)ntiles), dim3(256), 0, s, n, (const cplx*)A, lda, c,
+                         (const cplx*)w.tpart, nb1, w.scal, w.d, w.e, w.tau, w.P, nt);
       if (w.prof) w.prof->end(PROF_TRD_HEMV, 16.0 * np * (np + 1.0) * 0.5, s);
+      hipLaunchKernelGGL(k_trd_w, dim3(nt), dim3(256), 0, s, n, (const cplx*)A, lda, w.W, ldw, i0, j, c,
+                         (const cplx*)w.tpart, nb1, (const cplx*)w.P, nt, (const double*)w.scal,
+                         w.dpart);
+      ndp = nt;
     }
     const int cl = i0 + ib - 1;
     hipLaunchKernelGGL(k_trd_finish, dim3(ceil_div(n - cl - 1, 256)), dim3(256), 0, s, n, A, lda, w.W,
-                       ldw, ib - 1, cl, (const double*)w.scal);
+                       ldw, ib - 1, cl, (const double*)w.scal, (const cplx*)w.dpart, ndp);
     const int o2 = i0 + ib;
     if (o2 < n) {
       const int nn = n - o2;
       cplx* C = A + (long)o2 * lda + o2;
-      // C -= V W^H
-      ZGemm g1 = zgemm_args(nn, nn, ib, zop(A + (long)i0 * lda + o2, lda, 1),
+      // C -= [V W] [W V]^H  (one GEMM over a concatenated K of 2 ib)
+      ZGemm g1 = zgemm_args(nn, nn, 2 * ib, zop(A + (long)i0 * lda + o2, lda, 1),
                             zop(w.W + o2, ldw, 0, 1), C, lda, 1, make_double2(-1.0, 0.0),
                             make_double2(1.0, 0.0));
+      g1.kcat = ib;
+      g1.A2 = zop(w.W + o2, ldw, 1);
+      g1.B2 = zop(A + (long)i0 * lda + o2, lda, 0, 1);
       g1.lower_only = 1;
       zgemm(g1, nullptr, 0, s, w.prof);
-      // C -= W V^H
-      ZGemm g2 = zgemm_args(nn, nn, ib, zop(w.W + o2, ldw, 1),
-                            zop(A + (long)i0 * lda + o2, lda, 0, 1), C, lda, 1,
-                            make_double2(-1.0, 0.0), make_double2(1.0, 0.0));
-      g2.lower_only = 1;
-      zgemm(g2, nullptr, 0, s, w.prof);
     }
   }
   hipLaunchKernelGGL(k_trd_last, dim3(1), dim3(1), 0, s, n, (const cplx*)A, lda, w.d);

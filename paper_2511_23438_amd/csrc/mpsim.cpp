@@ -62,6 +62,10 @@ struct mps_sim {
   double* d_zsum = nullptr;
   std::vector<long> zsum_off;
 
+  int gprec = GEMM_F64;     // arithmetic of the contractions (theta, C, measurement)
+  mps_progress_fn progress = nullptr;
+  void* progress_ctx = nullptr;
+
   std::string err;
   int failed = 0;
 };
@@ -280,6 +284,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   g.d1 = d1; g.d2 = d2; g.b2 = b2; g.swap = swap;
   g.phase = nullptr;
   g.tag = PROF_THETA;
+  g.prec = h->gprec;
   if (gate) {
     int pi = p.coupled(ba, bb);
     if (pi >= 0) {
@@ -308,6 +313,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     // C = U^H M -> site i+1 (q x no)
     ZGemm gc = zgemm_args(q, (int)no, kg, zop(h->site[i], q, 1, 1), zop(h->theta, no, 0), h->site[i + 1],
                           no, 0, one, zero);
+    gc.prec = h->gprec;
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i + 1], (long)q * no, 3);
     ensure_log(h, h->nlog + 1);
@@ -327,6 +333,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     // C = M V -> site i (mo x q)
     ZGemm gc = zgemm_args((int)mo, q, kg, zop(h->theta, no, 0), zop(h->tmpB, q, 0), h->site[i], q, 0, one,
                           zero);
+    gc.prec = h->gprec;
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i], mo * q, 3);
     ensure_log(h, h->nlog + 1);
@@ -351,6 +358,8 @@ void run_step(mps_sim* h) {
   std::vector<Op> ops;
   std::vector<int> pos = h->pos;
   h->plan.step_ops(pos, ops);
+  int nu2 = 0, done = 0;
+  for (const Op& o : ops) nu2 += (o.kind == 1);
   for (size_t k = 0; k < ops.size(); ++k) {
     const Op& o = ops[k];
     if (o.kind == 1) {
@@ -358,6 +367,8 @@ void run_step(mps_sim* h) {
       for (size_t k2 = k + 1; k2 < ops.size(); ++k2)
         if (ops[k2].kind == 1) { next = ops[k2].site; break; }
       two_site(h, o.site, o.swap, o.gate, next);
+      ++done;
+      if (h->progress) h->progress(h->progress_ctx, h->steps, done, nu2);
     } else {
       single_site(h, o.site, o.variant);
     }
@@ -390,6 +401,7 @@ void measure_sweep(mps_sim* h, double out[3]) {
     ZGemm g1 = zgemm_args(b, d * b2, b, zop(h->env[cur], b, 0), zop(h->site[st], (long)d * b2, 0), h->envx,
                           (long)d * b2, 0, one, zero);
     g1.batch = 3;
+    g1.prec = h->gprec;
     g1.A.stride = (long)b * b;
     g1.B.stride = 0;
     g1.strideC = xs;
@@ -399,6 +411,7 @@ void measure_sweep(mps_sim* h, double out[3]) {
     ZGemm g2 = zgemm_args(b2, b2, b * d, zop(h->site[st], b2, 1, 1), zop(h->envx, b2, 0), h->env[1 - cur], b2,
                           0, one, zero);
     g2.batch = 3;
+    g2.prec = h->gprec;
     g2.A.stride = 0;
     g2.B.stride = xs;
     g2.strideC = (long)b2 * b2;
@@ -488,6 +501,8 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
   mps_sim* h = new mps_sim();
   h->cfg = *cfg;
   h->stream = (hipStream_t)hip_stream;
+  h->gprec = cfg->precision == MPS_C64_FP32ACC ? GEMM_F32
+           : cfg->precision == MPS_BF16X3_FP32ACC ? GEMM_BF16X3 : GEMM_F64;
   if (alloc) {
     h->alloc = *alloc;
     h->has_alloc = true;
@@ -829,6 +844,13 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len) {
     re_im[2 * x] = T[flat].real();
     re_im[2 * x + 1] = T[flat].imag();
   }
+  return MPS_OK;
+}
+
+mps_status mps_set_progress(mps_handle h, mps_progress_fn fn, void* ctx) {
+  GUARD(h);
+  h->progress = fn;
+  h->progress_ctx = ctx;
   return MPS_OK;
 }
 

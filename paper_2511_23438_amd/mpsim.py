@@ -57,6 +57,7 @@ class MpsObs(C.Structure):
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
 
@@ -89,6 +90,7 @@ _sig = {
     "mps_to_statevector": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64]),
     "mps_apply_trotter_step_batched": (C.c_int, [C.POINTER(H), C.c_int32, C.c_int32]),
     "mps_sync": (C.c_int, [H]),
+    "mps_set_progress": (C.c_int, [H, PROGRESS_FN, C.c_void_p]),
     "mps_profile": (C.c_int, [H, C.c_int32]),
     "mps_profile_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
@@ -227,6 +229,16 @@ class Simulation:
             self.free()
         except Exception:
             pass
+
+    def set_progress(self, fn) -> None:
+        """fn(step, update, updates_per_step) after each two-site update is
+        enqueued; None removes it."""
+        if fn is None:
+            self._progress = None
+            _check(_lib.mps_set_progress(self.h, PROGRESS_FN(), None), self.h)
+            return
+        self._progress = PROGRESS_FN(lambda ctx, s, u, n: fn(s, u, n))
+        _check(_lib.mps_set_progress(self.h, self._progress, None), self.h)
 
     # -- profiling ----------------------------------------------------------
     PROF = {"off": 0, "trd_hemv": 1, "gram": 2, "gemm": 3, "theta": 4}

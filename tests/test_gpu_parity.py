@@ -170,3 +170,24 @@ def test_random_state_truncating_parity(R, C, chi, init_chi, steps, seed):
     f_ora = np.array([u["f"] for u in ora.update_log])
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
     assert sim.bond_dims() == ora.bond_dims()
+
+
+@pytest.mark.parametrize("prec", ["c64", "bf16x3"])
+@pytest.mark.parametrize("R,C,chi,steps,seed", [(4, 4, 16, 3, 21), (3, 5, 24, 2, 22),
+                                                 (5, 6, 64, 1, 23)])
+def test_reduced_precision_against_fp64_oracle(prec, R, C, chi, steps, seed):
+    """Contractions in complex64 / bf16x3 with FP32 accumulation, truncation in
+    FP64: observables within 1e-5 of the FP64 oracle, F within 1e-5 relative."""
+    sites, centre = workloads.random_mps(R, C, chi, seed)
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, precision=prec))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(Grid(R, C), chi, sites, centre, J, H, DT)
+    for s_ in range(steps):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        ez, ez2 = abs(a["z"] - b["z"]), abs(a["z2"] - b["z2"])
+        ef = abs(a["fidelity"] - b["fidelity"]) / b["fidelity"]
+        print(prec, R, C, chi, "step", s_ + 1, "err z %.2e z2 %.2e F(rel) %.2e" % (ez, ez2, ef))
+        assert ez < 1e-5 and ez2 < 1e-5 and ef < 1e-5
+        assert abs(a["norm"] - 1) < 1e-5    # measured with reduced-precision contractions
