@@ -67,7 +67,7 @@ def read_traffic(kind: str, workload: str):
         return None
 
 
-def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float) -> dict:
+def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float, schedule: int = 1) -> dict:
     """Oracle (numpy, float64) timed on a bounded sample of the workload: one
     bulk two-site update of the same grid at a reduced bond dimension,
     extrapolated to chi by the cubic cost of its SVD and summed over the
@@ -106,7 +106,7 @@ def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float) -> dict:
     caps = [1] + [int(min(chi, d ** b, d ** (N - b))) for b in range(1, N)] + [1]
     step_s = 0.0
     nup = 0
-    for op in step_ops(g, g.snake()):
+    for op in step_ops(g, g.snake(), 1, schedule):
         if op[0] != "U2":
             continue
         i = op[1]
@@ -120,6 +120,23 @@ def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float) -> dict:
                                                        chi))}
 
 
+def served(time_limit: float, chi_cap: int, n_req: int, seed: int = 2511) -> dict:
+    """Continuous-batching run over a seeded Poisson trace (50 requests/s,
+    grids 4x4..7x8, chi log-uniform, 10-40 steps, complex64 contractions),
+    with chi capped so the run stays bounded; admission stops after
+    `time_limit` seconds and the admitted requests run to completion."""
+    import torch
+    from paper_2511_23438_amd import serve, workloads
+    trace = workloads.serving_trace(n_req, seed=seed, chi_max=chi_cap)
+    free, total = torch.cuda.mem_get_info()
+    srv = serve.Server(budget_bytes=int(0.5 * free), max_active=16, seed=seed)
+    out = srv.run(trace, time_limit_s=time_limit)
+    out.pop("results")
+    out.update({"requests_in_trace": n_req, "chi_cap": chi_cap, "precision": "c64",
+                "arrival_rate_per_s": 50.0})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,15 +145,21 @@ def main() -> int:
     ap.add_argument("--start", default="random", choices=["random", "product"])
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--pmc-sample", action="store_true",
-                    help="counter sample: a 1 GiB copy, then one bulk two-site update")
+                    help="counter sample: a 1 GiB elementwise kernel, then one bulk two-site update")
     ap.add_argument("--rows", type=int, default=6)
     ap.add_argument("--cols", type=int, default=8)
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "c64", "bf16x3"])
     ap.add_argument("--theta0", type=float, default=math.pi / 18)
+    ap.add_argument("--schedule", type=int, default=1, choices=[1, 2],
+                    help="1: wrap pairs routed by SWAPs and back; 2: rotating rows")
     ap.add_argument("--prof", default="trd_hemv", choices=sorted(DOMINANT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="admission window of the served run (0 disables it)")
+    ap.add_argument("--serve-chi-cap", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=8)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -151,7 +174,7 @@ def main() -> int:
     torch.cuda.set_device(0)
 
     cfg = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
-                            precision=args.precision)
+                            precision=args.precision, schedule=args.schedule)
     sim = mpsim.Simulation(cfg)
     if args.start == "random" or args.pmc_sample:
         from paper_2511_23438_amd import workloads
@@ -162,11 +185,12 @@ def main() -> int:
         del sites
         log("random start state loaded, bonds %s" % sim.bond_dims())
     if args.pmc_sample:
-        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        # calibration: an elementwise kernel that reads 1 GiB and writes 1 GiB
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
-        y.copy_(x)
+        torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
-        log("calibration copy of 1 GiB done")
+        log("calibration kernel (1 GiB read, 1 GiB written) done")
         t0 = time.perf_counter()
         sim.apply_two_site(args.rows - 1, 0, 1)
         sim.sync()
@@ -228,7 +252,8 @@ def main() -> int:
         "config": {"workload": workload, "rows": args.rows, "cols": args.cols,
                    "d": 2 ** ((args.cols + 1) // 2), "sites": 2 * args.rows, "chi": args.chi,
                    "precision": args.precision, "theta0": args.theta0, "J": -1.0, "h": 2.0,
-                   "dt": 0.25, "trotter_order": 1, "schedule": "block-pair",
+                   "dt": 0.25, "trotter_order": 1,
+                   "schedule": {1: "block-pair", 2: "rotating-rows"}[args.schedule],
                    "start": ("seeded random MPS at saturated bonds (seed %d)" % args.seed
                              if args.start == "random" else "product state")
                             + (" + %d warmup steps" % args.warmup if args.warmup else "")},
@@ -237,8 +262,16 @@ def main() -> int:
                         "norm": obs["norm"]},
     }
     sim.free()
+    if args.serve_seconds > 0:
+        log("served run: %d requests, chi <= %d, admission window %.0fs" % (
+            args.serve_requests, args.serve_chi_cap, args.serve_seconds))
+        out["served"] = served(args.serve_seconds, args.serve_chi_cap, args.serve_requests)
+        log("served: %s" % {k: out["served"][k] for k in ("completed", "steps_per_s",
+                                                         "step_latency_ms_p50",
+                                                         "step_latency_ms_p99")})
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget,
+                                           args.schedule)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -74,7 +74,8 @@ typedef struct {
   int32_t chi_max;         /* maximum bond dimension, >= 1 */
   int32_t precision;       /* mps_precision */
   int32_t trotter_order;   /* 1: exp(-i dt H_X) exp(-i dt H_ZZ); 2: eq. "trotter_step" */
-  int32_t schedule;        /* 1: the block-pair schedule (only value supported) */
+  int32_t schedule;        /* 1: wrap pairs routed by SWAPs and back (11R-12 updates/step);
+                              2: rotating rows (7R-8 / 7R-7 updates/step, even / odd R) */
   int32_t periodic;        /* 1: periodic in both directions (the paper's TFIM); 0: open */
   int32_t reserved;        /* must be 0 */
   double J, h, dt;         /* couplings and time step of eq. "hamiltonian" */

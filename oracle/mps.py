@@ -30,11 +30,12 @@ from .schedule import step_ops
 
 class BlockMPS:
     def __init__(self, grid: Grid, chi: int, theta0: float, J: float,
-                 h: float, dt: float, order: int = 1):
+                 h: float, dt: float, order: int = 1, schedule: int = 1):
         self.grid = grid
         self.chi = int(chi)
         self.J, self.h, self.dt = float(J), float(h), float(dt)
         self.order = int(order)
+        self.schedule = int(schedule)
         self.pos = grid.snake()
         self.sites = []
         for b in self.pos:
@@ -48,10 +49,10 @@ class BlockMPS:
 
     @classmethod
     def from_sites(cls, grid: Grid, chi: int, sites, centre: int, J: float, h: float,
-                   dt: float, order: int = 1) -> "BlockMPS":
+                   dt: float, order: int = 1, schedule: int = 1) -> "BlockMPS":
         """Start from given sites (snake block order, mixed canonical form
         with the norm on site ``centre``)."""
-        m = cls(grid, chi, 0.0, J, h, dt, order)
+        m = cls(grid, chi, 0.0, J, h, dt, order, schedule)
         m.sites = [np.array(a, dtype=np.complex128) for a in sites]
         m.centre = int(centre)
         return m
@@ -130,7 +131,7 @@ class BlockMPS:
         self.sites[p] = np.einsum('st,atb->asb', U, self.sites[p])
 
     def step(self) -> None:
-        for op in step_ops(self.grid, list(self.pos), self.order):
+        for op in step_ops(self.grid, list(self.pos), self.order, self.schedule):
             if op[0] == "U2":
                 _, site, swap, gate, a, b = op
                 assert (self.pos[site], self.pos[site + 1]) == (a, b)
@@ -210,9 +211,9 @@ class BlockMPS:
 
 
 def run(grid: Grid, chi: int, theta0: float, J: float, h: float, dt: float,
-        nsteps: int, order: int = 1) -> list[dict]:
+        nsteps: int, order: int = 1, schedule: int = 1) -> list[dict]:
     """Measurements at s = 0..nsteps (step 0 before any gate)."""
-    m = BlockMPS(grid, chi, theta0, J, h, dt, order)
+    m = BlockMPS(grid, chi, theta0, J, h, dt, order, schedule)
     out = [m.measure()]
     for _ in range(nsteps):
         m.step()

@@ -15,6 +15,14 @@ neighbours in the chain are brought together by SWAP updates. One step:
      the gate is applied, and it is swapped back;
   X  the single-site layer exp(-i h dt X) (times the intra-block ZZ phases).
 
+Schedule 2 (rotating rows) replaces W: phases A and C skip the facing pair
+between the last two chain rows; after B the last chain row moves to the
+chain front by SWAP updates (its first block to site 0, then its second to
+site 1), and the crossings with the blocks it is coupled to (same side in
+chain rows R-2 and 0) carry the phase gate. For odd R one pure SWAP first
+reverses the moving row so that chain rows keep facing same-side blocks.
+The chain order of the rows rotates by one row per step.
+
 Ops are tuples:
   ("U2", site, swap, gate, block_at_site, block_at_site_plus_1)
   ("U1", site, variant, block)   variant 0: U_X(h dt) * D_intra   (order 1)
@@ -26,10 +34,11 @@ from __future__ import annotations
 from .lattice import Grid, pair_coupled
 
 
-def step_ops(grid: Grid, pos: list[int], order: int = 1) -> list[tuple]:
+def step_ops(grid: Grid, pos: list[int], order: int = 1, schedule: int = 1) -> list[tuple]:
     """Ops of one Trotter step starting from chain order ``pos``; ``pos`` is
     updated in place to the order at the end of the step."""
     R = grid.rows
+    rotating = schedule == 2 and grid.periodic and R >= 3
     ops: list[tuple] = []
 
     def u2(site: int, swap: bool, gate: bool):
@@ -43,13 +52,21 @@ def step_ops(grid: Grid, pos: list[int], order: int = 1) -> list[tuple]:
     if order == 2:
         for p in range(len(pos)):
             ops.append(("U1", p, 1, pos[p]))
-    for r in range(R - 1):                      # A
+    nfacing = R - 2 if rotating else R - 1
+    for r in range(nfacing):                    # A
         u2(2 * r + 1, False, True)
     for r in range(R):                          # B
         u2(2 * r, True, True)
-    for r in range(R - 1):                      # C
+    for r in range(nfacing):                    # C
         u2(2 * r + 1, False, True)
-    if grid.periodic and R >= 3:                # W
+    if rotating:                                # last row to the front
+        if R % 2 == 1:
+            u2(2 * R - 2, True, False)
+        for p in range(2 * R - 3, -1, -1):
+            u2(p, True, True)
+        for p in range(2 * R - 2, 0, -1):
+            u2(p, True, True)
+    elif grid.periodic and R >= 3:              # W
         for p0 in (1, 0):
             target = 2 * (R - 1) + (pos[p0] % 2)
             t = pos.index(target)
@@ -63,9 +80,9 @@ def step_ops(grid: Grid, pos: list[int], order: int = 1) -> list[tuple]:
     return ops
 
 
-def schedule(grid: Grid, nsteps: int, order: int = 1) -> list[tuple]:
+def schedule(grid: Grid, nsteps: int, order: int = 1, schedule_id: int = 1) -> list[tuple]:
     pos = grid.snake()
     out = []
     for _ in range(nsteps):
-        out += step_ops(grid, pos, order)
+        out += step_ops(grid, pos, order, schedule_id)
     return out

@@ -65,23 +65,35 @@ static ZOp strided_op(const cplx* base, long rs, long cs, int conj = 0) {
 // fences cost a write-back of the per-XCD L2 on this part).
 // scal: [0] beta [1,2] tau [3,4] scale of the latest column.
 #define TP (2 * TRD_NB + 1)
+// workgroups of the mat-vec kernel; each loops over tiles
+#define HEMV_WGS 2048
 
-__device__ inline cplx trd_alpha(const double* scal, const cplx* dpart, int ndp) {
+// alpha = -(tau/2) * sum of the partial dot products y^H v of the previous
+// column, reduced by the whole workgroup (every thread must call it).
+__device__ inline cplx trd_alpha(const double* scal, const cplx* dpart, int ndp, double* sh) {
   cplx ds = make_double2(0.0, 0.0);
-  for (int b = 0; b < ndp; ++b) ds = cadd(ds, dpart[b]);
+  for (int b = threadIdx.x; b < ndp; b += blockDim.x) ds = cadd(ds, dpart[b]);
+  ds.x = block_sum(ds.x, sh);
+  ds.y = block_sum(ds.y, sh);
   return cscale(cmul(make_double2(scal[1], scal[2]), ds), -0.5);
 }
 
+// One workgroup per 64 rows of column c; wave q owns the panel columns
+// jj = q, q + 4, ... (their reflector and W entries stay in registers for
+// both the update and the dot products).
 __global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, cplx* W, long ldw, int i0,
                                                  int j, int c, const double* scal, const cplx* dpart,
                                                  int ndp, cplx* tpart) {
   __shared__ cplx wrow[TRD_NB], vrow[TRD_NB];
-  __shared__ cplx sh[4 * 64];
-  __shared__ cplx alpha_s;
-  const int t = threadIdx.x;
-  if (t == 0 && j > 0) alpha_s = trd_alpha(scal, dpart, ndp);
-  __syncthreads();
-  const cplx alpha = (j > 0) ? alpha_s : make_double2(0.0, 0.0);
+  __shared__ cplx part[4][64];
+  __shared__ cplx abuf[64];
+  __shared__ double dsh[4];
+  const int t = threadIdx.x, lane = t & 63, q = t >> 6;
+  const long r = c + (long)blockIdx.x * 64 + lane;
+  const bool in = r < n;
+  cplx a0 = make_double2(0.0, 0.0);
+  if (q == 0 && in) a0 = A[(long)c * lda + r];
+  const cplx alpha = (j > 0) ? trd_alpha(scal, dpart, ndp, dsh) : make_double2(0.0, 0.0);
   const cplx scp = make_double2(scal[3], scal[4]);
   if (t < j) {
     cplx wv = W[(long)t * ldw + c];
@@ -89,81 +101,87 @@ __global__ __launch_bounds__(256) void k_trd_col(int n, cplx* A, long lda, cplx*
     wrow[t] = cconj(wv);
     vrow[t] = (t == j - 1) ? make_double2(1.0, 0.0) : cconj(A[(long)(i0 + t) * lda + c]);
   }
-  __syncthreads();
-  const long r = c + (long)blockIdx.x * 256 + t;
-  cplx a = make_double2(0.0, 0.0), vprev = make_double2(0.0, 0.0), wfix = make_double2(0.0, 0.0);
-  if (r < n) {
-    if (j > 0) {
-      if (r == c) {
-        vprev = make_double2(1.0, 0.0);
-        wfix = cadd(W[(long)(j - 1) * ldw + r], alpha);
-      } else {
-        vprev = cmul(A[(long)(c - 1) * lda + r], scp);
-        A[(long)(c - 1) * lda + r] = vprev;
-        wfix = cadd(W[(long)(j - 1) * ldw + r], cmul(alpha, vprev));
-        W[(long)(j - 1) * ldw + r] = wfix;
-      }
-    }
-    a = A[(long)c * lda + r];
-    for (int jj = 0; jj < j; ++jj) {
-      const cplx v = (jj == j - 1) ? vprev : A[(long)(i0 + jj) * lda + r];
-      const cplx wv = (jj == j - 1) ? wfix : W[(long)jj * ldw + r];
-      a = csub(a, cadd(cmul(v, wrow[jj]), cmul(wv, vrow[jj])));
-    }
-    if (r == c) a.y = 0.0;
-    A[(long)c * lda + r] = a;
-  }
-  const bool act = (r < n) && (r >= c + 2);
-  const int count = 1 + 2 * j;
-  const int lane = t & 63, wv = t >> 6;
-  // values k < count: 0 -> |x|^2, 1..j -> conj(W[r, jj]) x, j+1..2j ->
-  // conj(V[r, jj]) x; reduced over the wave 16 at a time by a butterfly that
-  // halves the number of values held per lane at each exchange (16 -> 1),
-  // then two plain exchanges.
-  for (int g0 = 0; g0 < count; g0 += 16) {
-    cplx vals[16];
+  cplx vv[8], ww[8];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int kk = g0 + u;
-      cplx v = make_double2(0.0, 0.0);
-      if (act && kk < count) {
-        if (kk == 0) {
-          v = make_double2(cabs2(a), 0.0);
+  for (int u = 0; u < 8; ++u) {
+    const int jj = q + 4 * u;
+    cplx v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
+    if (in && jj < j) {
+      if (jj == j - 1) {
+        // the previous column: scale its reflector, add alpha v to its W
+        if (r == c) {
+          v = make_double2(1.0, 0.0);
+          w = cadd(W[(long)jj * ldw + r], alpha);
         } else {
-          const int jj = (kk <= j) ? kk - 1 : kk - 1 - j;
-          if (kk <= j) v = cmulc((jj == j - 1) ? wfix : W[(long)jj * ldw + r], a);
-          else v = cmulc((jj == j - 1) ? vprev : A[(long)(i0 + jj) * lda + r], a);
+          v = cmul(A[(long)(c - 1) * lda + r], scp);
+          A[(long)(c - 1) * lda + r] = v;
+          w = cadd(W[(long)jj * ldw + r], cmul(alpha, v));
+          W[(long)jj * ldw + r] = w;
         }
-      }
-      vals[u] = v;
-    }
-#pragma unroll
-    for (int half = 8, m = 32; half >= 1; half >>= 1, m >>= 1) {
-      const bool upper = (lane & m) != 0;
-#pragma unroll
-      for (int q2 = 0; q2 < half; ++q2) {
-        const cplx keep = upper ? vals[q2 + half] : vals[q2];
-        const cplx send = upper ? vals[q2] : vals[q2 + half];
-        cplx got;
-        got.x = __shfl_xor(send.x, m, 64);
-        got.y = __shfl_xor(send.y, m, 64);
-        vals[q2] = cadd(keep, got);
+      } else {
+        v = A[(long)(i0 + jj) * lda + r];
+        w = W[(long)jj * ldw + r];
       }
     }
-    cplx z = vals[0];
-    z.x += __shfl_xor(z.x, 2, 64);
-    z.y += __shfl_xor(z.y, 2, 64);
-    z.x += __shfl_xor(z.x, 1, 64);
-    z.y += __shfl_xor(z.y, 1, 64);
-    if ((lane & 3) == 0) {
-      const int vid = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
-                      ((lane >> 2) & 1);
-      sh[wv * 64 + g0 + vid] = z;
-    }
+    vv[u] = v;
+    ww[u] = w;
   }
   __syncthreads();
-  if (t < count)
-    tpart[(long)blockIdx.x * TP + t] = cadd(cadd(sh[t], sh[64 + t]), cadd(sh[128 + t], sh[192 + t]));
+  cplx s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int jj = q + 4 * u;
+    if (jj < j) s = cadd(s, cadd(cmul(vv[u], wrow[jj]), cmul(ww[u], vrow[jj])));
+  }
+  part[q][lane] = s;
+  __syncthreads();
+  if (q == 0) {
+    cplx a = csub(a0, cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane])));
+    if (r == c) a.y = 0.0;
+    if (in) A[(long)c * lda + r] = a;
+    abuf[lane] = a;
+  }
+  __syncthreads();
+  const cplx a = abuf[lane];
+  const bool act = in && r >= c + 2;
+  // values u < 8: conj(W[r, jj]) x, u >= 8: conj(V[r, jj]) x for jj = q + 4 (u mod 8);
+  // reduced over the wave by a butterfly that halves the number of values
+  // held per lane at each exchange (16 -> 1), then two plain exchanges
+  cplx vals[16];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const bool ok = act && (q + 4 * u) < j;
+    vals[u] = ok ? cmulc(ww[u], a) : make_double2(0.0, 0.0);
+    vals[8 + u] = ok ? cmulc(vv[u], a) : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int half = 8, m = 32; half >= 1; half >>= 1, m >>= 1) {
+    const bool upper = (lane & m) != 0;
+#pragma unroll
+    for (int q2 = 0; q2 < half; ++q2) {
+      const cplx keep = upper ? vals[q2 + half] : vals[q2];
+      const cplx send = upper ? vals[q2] : vals[q2 + half];
+      cplx got;
+      got.x = __shfl_xor(send.x, m, 64);
+      got.y = __shfl_xor(send.y, m, 64);
+      vals[q2] = cadd(keep, got);
+    }
+  }
+  cplx z = vals[0];
+  z.x += __shfl_xor(z.x, 2, 64);
+  z.y += __shfl_xor(z.y, 2, 64);
+  z.x += __shfl_xor(z.x, 1, 64);
+  z.y += __shfl_xor(z.y, 1, 64);
+  if ((lane & 3) == 0) {
+    const int vid = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+                    ((lane >> 2) & 1);
+    const int jj = q + 4 * (vid & 7);
+    if (jj < j) tpart[(long)blockIdx.x * TP + (vid < 8 ? 1 + jj : 1 + j + jj)] = z;
+  }
+  if (q == 0) {
+    const double x2 = wave_sum(act ? cabs2(a) : 0.0);
+    if (lane == 0) tpart[(long)blockIdx.x * TP] = make_double2(x2, 0.0);
+  }
 }
 
 __device__ inline cplx trd_v(const cplx* A, long lda, int n, int c, long r, cplx sc) {
@@ -174,143 +192,192 @@ __device__ inline cplx trd_v(const cplx* A, long lda, int n, int c, long r, cplx
 
 // y = A22 v over the lower-triangle tiles (64 x 64) of the trailing matrix;
 // tile (I, J) writes A_IJ v_J to P[I][J] and, off the diagonal, A_IJ^H v_I to
-// P[J][I].
-__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, int c,
-                                                     const cplx* tpart, int nparts, double* scal,
-                                                     double* d, double* e, cplx* tau, cplx* P, int nt) {
+// P[J][I]. Each workgroup forms the reflector once, then loops over tiles.
+__global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda, int c, int j,
+                                                     const cplx* tpart, int nparts, cplx* tsum,
+                                                     double* scal, double* d, double* e, cplx* tau,
+                                                     cplx* P, int nt, long ntiles) {
   __shared__ cplx vI[64], vJ[64];
   __shared__ cplx red[4][64];
   __shared__ cplx sc_s;
   const int t = threadIdx.x;
-  if (t == 0) {
+  const int lane = t & 63, wq = t >> 6;
+  if (blockIdx.x == 0) {
+    // workgroup 0 also reduces W^H x and V^H x (values 1..2j) for the
+    // finalising kernel: wave wq sums the parts b = wq, wq + 4, ...
+    const int k = 1 + lane;
+    cplx acc = make_double2(0.0, 0.0);
+    if (k <= 2 * j) {
+#pragma unroll 8
+      for (int b = wq; b < nparts; b += 4) acc = cadd(acc, tpart[(long)b * TP + k]);
+    }
+    red[wq][lane] = acc;
+    __syncthreads();
+    if (wq == 0 && k <= 2 * j)
+      tsum[k] = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+    __syncthreads();
+  }
+  if (wq == 0) {
     // reflector of column c from |x|^2 (partials of the column kernel)
     double xn = 0.0;
-    for (int b = 0; b < nparts; ++b) xn += tpart[(long)b * TP].x;
-    double beta;
-    cplx tauv, scl;
-    reflector(A[(long)c * lda + c + 1], xn, beta, tauv, scl);
-    sc_s = scl;
-    if (blockIdx.x == 0) {
-      scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = scl.x; scal[4] = scl.y;
-      tau[c] = tauv;
-      e[c] = beta;
-      d[c] = A[(long)c * lda + c].x;
+    for (int b = lane; b < nparts; b += 64) xn += tpart[(long)b * TP].x;
+    xn = wave_sum(xn);
+    if (lane == 0) {
+      double beta;
+      cplx tauv, scl;
+      reflector(A[(long)c * lda + c + 1], xn, beta, tauv, scl);
+      sc_s = scl;
+      if (blockIdx.x == 0) {
+        scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = scl.x; scal[4] = scl.y;
+        tau[c] = tauv;
+        e[c] = beta;
+        d[c] = A[(long)c * lda + c].x;
+      }
     }
   }
   __syncthreads();
-  const long k = blockIdx.x;
-  long I = (long)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > k) --I;
-  while ((I + 1) * (I + 2) / 2 <= k) ++I;
-  const long J = k - I * (I + 1) / 2;
   const int o = c + 1;
   const cplx sc = sc_s;
-  if (t < 64) vI[t] = trd_v(A, lda, n, c, o + I * 64 + t, sc);
-  else if (t < 128) vJ[t - 64] = trd_v(A, lda, n, c, o + J * 64 + (t - 64), sc);
-  __syncthreads();
-  const int rr = t & 63, cg = t >> 6;
-  const long row = o + I * 64 + rr;
-  cplx y = make_double2(0.0, 0.0);
-  if (I == J) {
-    for (int cc = 0; cc < 16; ++cc) {
-      const int cl = cg * 16 + cc;
-      const long col = o + J * 64 + cl;
-      cplx a = make_double2(0.0, 0.0);
-      if (row < n && col < n) {
-        if (cl < rr) a = A[col * lda + row];
-        else if (cl > rr) a = cconj(A[row * lda + col]);
-        else a = make_double2(A[col * lda + row].x, 0.0);
+  const int rr = lane, cg = wq;
+#pragma unroll 1
+  for (long k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    // tile order: column block J outer (descending), row block I inner, so
+    // workgroups running together read neighbouring segments of the same 64
+    // columns
+    long a = (long)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+    while (a * (a + 1) / 2 > k) --a;
+    while ((a + 1) * (a + 2) / 2 <= k) ++a;
+    const long b = k - a * (a + 1) / 2;
+    const long J = nt - 1 - a, I = nt - 1 - b;
+    if (t < 64) vI[t] = trd_v(A, lda, n, c, o + I * 64 + t, sc);
+    else if (t < 128) vJ[t - 64] = trd_v(A, lda, n, c, o + J * 64 + (t - 64), sc);
+    __syncthreads();
+    const long row = o + I * 64 + rr;
+    cplx y = make_double2(0.0, 0.0);
+    if (I == J) {
+#pragma unroll 1
+      for (int cc = 0; cc < 16; ++cc) {
+        const int cl = cg * 16 + cc;
+        const long col = o + J * 64 + cl;
+        cplx av = make_double2(0.0, 0.0);
+        if (row < n && col < n) {
+          if (cl < rr) av = A[col * lda + row];
+          else if (cl > rr) av = cconj(A[row * lda + col]);
+          else av = make_double2(A[col * lda + row].x, 0.0);
+        }
+        y = cadd(y, cmul(av, vJ[cl]));
       }
-      y = cadd(y, cmul(a, vJ[cl]));
-    }
-  } else {
-    const cplx vi = vI[rr];
+    } else {
+      const cplx vi = vI[rr];
+#pragma unroll 1
+      for (int g8 = 0; g8 < 2; ++g8) {
+        cplx av[8];
 #pragma unroll
-    for (int g8 = 0; g8 < 2; ++g8) {
-      cplx av[8];
+        for (int cc = 0; cc < 8; ++cc) {
+          const long col = o + J * 64 + cg * 16 + g8 * 8 + cc;
+          av[cc] = (row < n && col < n) ? A[col * lda + row] : make_double2(0.0, 0.0);
+        }
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc) {
-        const long col = o + J * 64 + cg * 16 + g8 * 8 + cc;
-        av[cc] = (row < n && col < n) ? A[col * lda + row] : make_double2(0.0, 0.0);
-      }
+        for (int cc = 0; cc < 8; ++cc) {
+          y = cadd(y, cmul(av[cc], vJ[cg * 16 + g8 * 8 + cc]));
+          av[cc] = cmulc(av[cc], vi);
+        }
+        // column sums over the 64 lanes: butterfly halving the values held
+        // per lane (8 -> 1), then three plain exchanges
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc) {
-        y = cadd(y, cmul(av[cc], vJ[cg * 16 + g8 * 8 + cc]));
-        av[cc] = cmulc(av[cc], vi);
-      }
-      // column sums over the 64 lanes: butterfly halving the values held per
-      // lane (8 -> 1), then three plain exchanges
+        for (int half = 4, m = 32; half >= 1; half >>= 1, m >>= 1) {
+          const bool upper = (rr & m) != 0;
 #pragma unroll
-      for (int half = 4, m = 32; half >= 1; half >>= 1, m >>= 1) {
-        const bool upper = (rr & m) != 0;
+          for (int q2 = 0; q2 < half; ++q2) {
+            const cplx keep = upper ? av[q2 + half] : av[q2];
+            const cplx send = upper ? av[q2] : av[q2 + half];
+            cplx got;
+            got.x = __shfl_xor(send.x, m, 64);
+            got.y = __shfl_xor(send.y, m, 64);
+            av[q2] = cadd(keep, got);
+          }
+        }
+        cplx z = av[0];
 #pragma unroll
-        for (int q2 = 0; q2 < half; ++q2) {
-          const cplx keep = upper ? av[q2 + half] : av[q2];
-          const cplx send = upper ? av[q2] : av[q2 + half];
-          cplx got;
-          got.x = __shfl_xor(send.x, m, 64);
-          got.y = __shfl_xor(send.y, m, 64);
-          av[q2] = cadd(keep, got);
+        for (int m = 4; m >= 1; m >>= 1) {
+          z.x += __shfl_xor(z.x, m, 64);
+          z.y += __shfl_xor(z.y, m, 64);
+        }
+        // lane rr holds the sum for column b3 + 2 b4 + 4 b5 of this group
+        if ((rr & 7) == 0) {
+          const int colid = ((rr >> 5) & 1) * 4 + ((rr >> 4) & 1) * 2 + ((rr >> 3) & 1);
+          P[(J * nt + I) * 64 + cg * 16 + g8 * 8 + colid] = z;
         }
       }
-      cplx z = av[0];
-#pragma unroll
-      for (int m = 4; m >= 1; m >>= 1) {
-        z.x += __shfl_xor(z.x, m, 64);
-        z.y += __shfl_xor(z.y, m, 64);
-      }
-      // lane rr holds the sum for column b3 + 2 b4 + 4 b5 of this group
-      if ((rr & 7) == 0) {
-        const int colid = ((rr >> 5) & 1) * 4 + ((rr >> 4) & 1) * 2 + ((rr >> 3) & 1);
-        P[(J * nt + I) * 64 + cg * 16 + g8 * 8 + colid] = z;
-      }
     }
+    red[cg][rr] = y;
+    __syncthreads();
+    if (t < 64) P[(I * nt + J) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
   }
-  red[cg][rr] = y;
-  __syncthreads();
-  if (t < 64) P[(I * nt + J) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
 }
 
-// One workgroup per 64-row block: 4 threads per row sum every fourth tile
-// partial (neighbouring lanes read neighbouring rows), then the corrections.
+// One workgroup per 64-row block: wave q sums the tile partials J = q, q+4, ...
+// of its rows and subtracts the panel corrections of columns jj = q, q+4, ...;
+// wave 0 combines, scales by tau into the new W column and reduces y^H v.
 __global__ __launch_bounds__(256) void k_trd_w(int n, const cplx* A, long lda, cplx* W, long ldw, int i0,
-                                               int j, int c, const cplx* tpart, int nparts,
+                                               int j, int c, const cplx* tsum,
                                                const cplx* P, int nt, const double* scal,
                                                cplx* dpart) {
   __shared__ cplx t1[TRD_NB], t2[TRD_NB];
   __shared__ cplx part[4][64];
-  __shared__ double dsh[4];
   const int t = threadIdx.x;
+  const int x = t & 63, q = t >> 6;
   const int o = c + 1;
   const cplx tauv = make_double2(scal[1], scal[2]);
   const cplx sc = make_double2(scal[3], scal[4]);
   if (t < 2 * j) {
-    // W^H x (t < j) and V^H x (t >= j) from the column partials
-    cplx acc = make_double2(0.0, 0.0);
-    for (int b = 0; b < nparts; ++b) acc = cadd(acc, tpart[(long)b * TP + 1 + t]);
+    // W^H x (t < j) and V^H x (t >= j), reduced by the mat-vec's workgroup 0
+    const cplx acc = tsum[1 + t];
     if (t < j) t1[t] = cadd(cconj(W[(long)t * ldw + o]), cmul(sc, acc));
     else t2[t - j] = cadd(cconj(A[(long)(i0 + t - j) * lda + o]), cmul(sc, acc));
   }
   const long I = blockIdx.x;
-  const int x = t & 63, q = t >> 6;
-  cplx acc = make_double2(0.0, 0.0);
-  for (long Jb = q; Jb < nt; Jb += 4) acc = cadd(acc, P[(I * nt + Jb) * 64 + x]);
-  part[q][x] = acc;
-  __syncthreads();
-  cplx y = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
   const long r = o + I * 64 + x;
-  if (t < 64 && r < n) {
-    y = cadd(cadd(part[0][x], part[1][x]), cadd(part[2][x], part[3][x]));
-    for (int jj = 0; jj < j; ++jj)
-      y = csub(y, cadd(cmul(A[(long)(i0 + jj) * lda + r], t1[jj]), cmul(W[(long)jj * ldw + r], t2[jj])));
-    y = cmul(tauv, y);
-    W[(long)j * ldw + r] = y;
-    v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
+  const bool in = r < n;
+  const cplx* Pr = P + I * nt * 64 + x;
+  cplx s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+  long Jb = q;
+  for (; Jb + 12 < nt; Jb += 16) {
+    s0 = cadd(s0, Pr[Jb * 64]);
+    s1 = cadd(s1, Pr[(Jb + 4) * 64]);
+    s2 = cadd(s2, Pr[(Jb + 8) * 64]);
+    s3 = cadd(s3, Pr[(Jb + 12) * 64]);
   }
-  const cplx dt = cmulc(y, v);
-  const double dre = block_sum(dt.x, dsh);
-  const double dim = block_sum(dt.y, dsh);
-  if (t == 0) dpart[blockIdx.x] = make_double2(dre, dim);
+  for (; Jb < nt; Jb += 4) s0 = cadd(s0, Pr[Jb * 64]);
+  cplx av[8], wv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int jj = q + 4 * u;
+    av[u] = (in && jj < j) ? A[(long)(i0 + jj) * lda + r] : make_double2(0.0, 0.0);
+    wv[u] = (in && jj < j) ? W[(long)jj * ldw + r] : make_double2(0.0, 0.0);
+  }
+  cplx v = make_double2(0.0, 0.0);
+  if (q == 0 && in) v = (r == o) ? make_double2(1.0, 0.0) : cmul(A[(long)c * lda + r], sc);
+  __syncthreads();
+  cplx s = cadd(cadd(s0, s1), cadd(s2, s3));
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int jj = q + 4 * u;
+    if (jj < j) s = csub(s, cadd(cmul(av[u], t1[jj]), cmul(wv[u], t2[jj])));
+  }
+  part[q][x] = s;
+  __syncthreads();
+  if (q == 0) {
+    cplx y = make_double2(0.0, 0.0);
+    if (in) {
+      y = cmul(tauv, cadd(cadd(part[0][x], part[1][x]), cadd(part[2][x], part[3][x])));
+      W[(long)j * ldw + r] = y;
+    }
+    const cplx dt = cmulc(y, v);
+    const double dre = wave_sum(dt.x);
+    const double dim = wave_sum(dt.y);
+    if (x == 0) dpart[blockIdx.x] = make_double2(dre, dim);
+  }
 }
 
 // Last column of a panel: scale its reflector, store the unit entry and add
@@ -318,10 +385,8 @@ __global__ __launch_bounds__(256) void k_trd_w(int n, const cplx* A, long lda, c
 __global__ __launch_bounds__(256) void k_trd_finish(int n, cplx* A, long lda, cplx* W, long ldw, int j,
                                                     int c, const double* scal, const cplx* dpart,
                                                     int ndp) {
-  __shared__ cplx alpha_s;
-  if (threadIdx.x == 0) alpha_s = trd_alpha(scal, dpart, ndp);
-  __syncthreads();
-  const cplx alpha = alpha_s;
+  __shared__ double dsh[4];
+  const cplx alpha = trd_alpha(scal, dpart, ndp, dsh);
   const cplx sc = make_double2(scal[3], scal[4]);
   const long r = c + 1 + (long)blockIdx.x * 256 + threadIdx.x;
   if (r >= n) return;
@@ -343,18 +408,19 @@ void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
     const int ib = std::min(TRD_NB, n - 1 - i0);
     for (int j = 0; j < ib; ++j) {
       const int c = i0 + j;
-      const int nb1 = ceil_div(n - c, 256);
+      const int nb1 = ceil_div(n - c, 64);
       hipLaunchKernelGGL(k_trd_col, dim3(nb1), dim3(256), 0, s, n, A, lda, w.W, ldw, i0, j, c,
                          (const double*)w.scal, (const cplx*)w.dpart, ndp, w.tpart);
       const int np = n - c - 1;
       const int nt = ceil_div(np, 64);
       const long ntiles = (long)nt * (nt + 1) / 2;
+      const unsigned grid = (unsigned)std::min<long>(std::max<long>(ntiles, 1), HEMV_WGS);
       if (w.prof) w.prof->begin(PROF_TRD_HEMV, s);
-      hipLaunchKernelGGL(k_trd_hemv, dim3((unsigned)ntiles), dim3(256), 0, s, n, (const cplx*)A, lda, c,
-                         (const cplx*)w.tpart, nb1, w.scal, w.d, w.e, w.tau, w.P, nt);
+      hipLaunchKernelGGL(k_trd_hemv, dim3(grid), dim3(256), 0, s, n, (const cplx*)A, lda, c, j,
+                         (const cplx*)w.tpart, nb1, w.tsum, w.scal, w.d, w.e, w.tau, w.P, nt, ntiles);
       if (w.prof) w.prof->end(PROF_TRD_HEMV, 16.0 * np * (np + 1.0) * 0.5, s);
       hipLaunchKernelGGL(k_trd_w, dim3(nt), dim3(256), 0, s, n, (const cplx*)A, lda, w.W, ldw, i0, j, c,
-                         (const cplx*)w.tpart, nb1, (const cplx*)w.P, nt, (const double*)w.scal,
+                         (const cplx*)w.tsum, (const cplx*)w.P, nt, (const double*)w.scal,
                          w.dpart);
       ndp = nt;
     }
@@ -435,21 +501,32 @@ __device__ inline int sturm_count(int n, const double* d, const double* e2, doub
   return cnt;
 }
 
-__global__ void k_bisect(int n, const double* d, const double* e2, int lo, int cnt,
-                         const double* bounds, double* lam) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// Multisection: one wave per wanted eigenvalue. Each round the 64 lanes
+// evaluate Sturm counts at 64 interior points of the current interval and a
+// ballot keeps the sub-interval that contains the eigenvalue, so the interval
+// shrinks 65-fold per round.
+__global__ __launch_bounds__(64) void k_bisect(int n, const double* d, const double* e2, int lo, int cnt,
+                                               const double* bounds, double* lam) {
+  const int k = blockIdx.x;
   if (k >= cnt) return;
+  const int lane = threadIdx.x;
   const int idx = lo + k;
   double a = bounds[0], b = bounds[1];
   const double atol = DBL_EPSILON * bounds[2], pivmin = bounds[3];
-  for (int it = 0; it < 256; ++it) {
+  for (int it = 0; it < 64; ++it) {
     if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + atol) break;
-    const double mid = 0.5 * (a + b);
-    if (mid <= a || mid >= b) break;
-    if (sturm_count(n, d, e2, mid, pivmin) > idx) b = mid;
-    else a = mid;
+    const double x = a + (b - a) * (double)(lane + 1) / 65.0;
+    const bool above = sturm_count(n, d, e2, x, pivmin) > idx;
+    const unsigned long long mask = __ballot(above);
+    // counts are monotone in x: the lanes above the eigenvalue form a suffix
+    const int f = (mask == 0ULL) ? 64 : __ffsll((long long)mask) - 1;
+    const double na = (f == 0) ? a : a + (b - a) * (double)f / 65.0;
+    const double nb = (f == 64) ? b : a + (b - a) * (double)(f + 1) / 65.0;
+    if (!(na > a || nb < b)) break;
+    a = na;
+    b = nb;
   }
-  lam[k] = 0.5 * (a + b);
+  if (lane == 0) lam[k] = 0.5 * (a + b);
 }
 
 __device__ inline double hash_uniform(uint64_t seed, uint64_t a, uint64_t b) {
@@ -485,6 +562,7 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double* d, const doub
   // the next row's sub/diag/super come from d, e.
   double di = d[0] - lmb;
   double ui = (n > 1) ? e[0] : 0.0;
+#pragma unroll 8
   for (int i = 0; i < n - 1; ++i) {
     const double li = e[i];
     const double dn = d[i + 1] - lmb;
@@ -518,6 +596,7 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double* d, const doub
   for (int it = 0; it < 3; ++it) {
     // forward: apply the row interchanges and multipliers
     double cur = AT(xx, 0);
+#pragma unroll 8
     for (int i = 0; i < n - 1; ++i) {
       const double nxt = AT(xx, i + 1);
       if (AT(pv, i) == 0.0) {
@@ -540,6 +619,7 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double* d, const doub
       x1 = v;
     }
     double mx = fmax(fabs(x1), fabs(x2));
+#pragma unroll 8
     for (int i = n - 3; i >= 0; --i) {
       const double v = (AT(xx, i) - AT(fu, i) * x1 - AT(fu2, i) * x2) / AT(fd, i);
       AT(xx, i) = v;
@@ -565,7 +645,7 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double* d, const doub
 void tridiag_eigvals(int n, int lo, int cnt, LinalgWork& w, hipStream_t s) {
   hipLaunchKernelGGL(k_trd_prep, dim3(1), dim3(256), 0, s, n, (const double*)w.d, (const double*)w.e,
                      w.e2, w.scal + 8);
-  hipLaunchKernelGGL(k_bisect, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, n, (const double*)w.d,
+  hipLaunchKernelGGL(k_bisect, dim3(cnt), dim3(64), 0, s, n, (const double*)w.d,
                      (const double*)w.e2, lo, cnt, (const double*)(w.scal + 8), w.lam);
 }
 
@@ -598,21 +678,25 @@ __global__ void k_extract_v(const cplx* A, long rs, long cs, int row0, int col0,
 // Forward column-wise block reflector factor: T upper (ib x ib, row-major
 // ld 64) with H_0 ... H_{ib-1} = I - V T V^H, from S = V^H V and tau.
 __global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx* tau, cplx* T) {
-  __shared__ cplx tcol[64];
+  __shared__ cplx Ts[64][65];
+  __shared__ cplx Ss[64][65];
   const int i = threadIdx.x;
-  for (int r = 0; r < 64; ++r) T[r * 64 + i] = make_double2(0.0, 0.0);
+  for (int r = 0; r < 64; ++r) {
+    Ts[r][i] = make_double2(0.0, 0.0);
+    Ss[r][i] = (r < ib && i < ib) ? S[r * 64 + i] : make_double2(0.0, 0.0);
+  }
   __syncthreads();
   for (int j = 0; j < ib; ++j) {
     const cplx mt = cscale(tau[j], -1.0);
     cplx acc = make_double2(0.0, 0.0);
     if (i < j)
-      for (int l = i; l < j; ++l) acc = cadd(acc, cmul(T[i * 64 + l], cmul(mt, S[l * 64 + j])));
-    tcol[i] = acc;
+      for (int l = i; l < j; ++l) acc = cadd(acc, cmul(Ts[i][l], Ss[l][j]));
     __syncthreads();
-    if (i < j) T[i * 64 + j] = tcol[i];
-    if (i == j) T[j * 64 + j] = tau[j];
+    if (i < j) Ts[i][j] = cmul(mt, acc);
+    if (i == j) Ts[j][j] = tau[j];
     __syncthreads();
   }
+  for (int r = 0; r < 64; ++r) T[r * 64 + i] = Ts[r][i];
 }
 
 static void block_reflector(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib,

@@ -23,7 +23,7 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   if (cfg->chi_max > 4096) { *msg = "chi_max > 4096 unsupported"; return MPS_E_UNSUPPORTED; }
   if (cfg->precision < 0 || cfg->precision > 2) { *msg = "bad precision"; return MPS_E_INVAL; }
   if (cfg->trotter_order != 1 && cfg->trotter_order != 2) { *msg = "trotter_order must be 1 or 2"; return MPS_E_INVAL; }
-  if (cfg->schedule != 1) { *msg = "only schedule 1 is supported"; return MPS_E_UNSUPPORTED; }
+  if (cfg->schedule != 1 && cfg->schedule != 2) { *msg = "schedule must be 1 or 2"; return MPS_E_INVAL; }
   if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
   if (cfg->reserved != 0) { *msg = "reserved must be 0"; return MPS_E_INVAL; }
   if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
@@ -55,17 +55,27 @@ void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
     o.kind = 2; o.site = site; o.variant = variant; o.block_a = pos[site]; o.block_b = -1;
     out.push_back(o);
   };
+  const bool rotating = schedule == 2 && periodic && R >= 3;
+  const int nfacing = rotating ? R - 2 : R - 1;
   if (order == 2)
     for (int p = 0; p < N; ++p) u1(p, 1);
-  // vertical neighbours facing each other between rows r and r+1
-  for (int r = 0; r + 1 < R; ++r) u2(2 * r + 1, 0, 1);
+  // vertical neighbours facing each other between chain rows r and r+1
+  for (int r = 0; r < nfacing; ++r) u2(2 * r + 1, 0, 1);
   // the two blocks of every row, fused with a SWAP
   for (int r = 0; r < R; ++r) u2(2 * r, 1, 1);
   // the other vertical neighbours, now facing each other
-  for (int r = 0; r + 1 < R; ++r) u2(2 * r + 1, 0, 1);
-  // periodic wrap between the last and the first row: route the last-row
-  // block next to its row-0 partner, gate, route back
-  if (periodic && R >= 3) {
+  for (int r = 0; r < nfacing; ++r) u2(2 * r + 1, 0, 1);
+  if (rotating) {
+    // rotating rows: the last chain row moves to the chain front; crossings
+    // with the blocks it is coupled to (chain rows R-2 and 0) carry the gate.
+    // For odd R the row is reversed first so chain rows keep facing
+    // same-side blocks.
+    if (R % 2 == 1) u2(2 * R - 2, 1, 0);
+    for (int p = 2 * R - 3; p >= 0; --p) u2(p, 1, 1);
+    for (int p = 2 * R - 2; p >= 1; --p) u2(p, 1, 1);
+  } else if (periodic && R >= 3) {
+    // periodic wrap between the last and the first row: route the last-row
+    // block next to its row-0 partner, gate, route back
     for (int p0 = 1; p0 >= 0; --p0) {
       int want = 2 * (R - 1) + (pos[p0] & 1);
       int t = (int)(std::find(pos.begin(), pos.end(), want) - pos.begin());
@@ -82,6 +92,7 @@ static int zval(int s, int w, int j) { return 1 - 2 * ((s >> (w - 1 - j)) & 1); 
 void build_plan(const mps_config* cfg, Plan& p) {
   p.R = cfg->rows; p.C = cfg->cols; p.n = p.R * p.C; p.N = 2 * p.R;
   p.chi = cfg->chi_max; p.order = cfg->trotter_order; p.periodic = cfg->periodic;
+  p.schedule = cfg->schedule;
   p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
   p.wL = (p.C + 1) / 2; p.wR = p.C / 2;
   p.dmax = 1 << p.wL;

@@ -126,7 +126,8 @@ def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
 
 def config_from_instance(inst, seed: int = 0) -> MpsConfig:
     return make_config(inst.rows, inst.cols, inst.chi, inst.J, inst.h, inst.dt,
-                       inst.theta0, inst.order, inst.precision, True, seed)
+                       inst.theta0, inst.order, inst.precision, True, seed,
+                       getattr(inst, "schedule", 1))
 
 
 def footprint_bytes(cfg: MpsConfig) -> int:

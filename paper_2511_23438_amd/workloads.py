@@ -28,6 +28,7 @@ class Instance:
     steps: int = PAPER_STEPS
     order: int = 1
     precision: str = "fp64"          # fp64 | c64 | bf16x3
+    schedule: int = 1                # 1: routed wrap pairs, 2: rotating rows
     name: str = ""
 
     def as_dict(self):

@@ -32,10 +32,11 @@ def test_header_symbols_exported():
 @pytest.mark.parametrize("R,C", [(4, 4), (5, 6), (6, 8), (7, 8), (3, 3), (4, 5), (1, 4),
                                  (2, 3), (5, 5)])
 @pytest.mark.parametrize("order", [1, 2])
-def test_schedule_equals_oracle(R, C, order):
-    cfg = mpsim.make_config(R, C, 16, order=order)
+@pytest.mark.parametrize("sched", [1, 2])
+def test_schedule_equals_oracle(R, C, order, sched):
+    cfg = mpsim.make_config(R, C, 16, order=order, schedule=sched)
     got = mpsim.schedule_dump(cfg, 3)
-    ref = oracle_schedule(Grid(R, C), 3, order)
+    ref = oracle_schedule(Grid(R, C), 3, order, sched)
     assert len(got) == len(ref)
     for row, op in zip(got, ref):
         if op[0] == "U2":
@@ -47,7 +48,7 @@ def test_schedule_equals_oracle(R, C, order):
 @pytest.mark.parametrize("kw,status", [
     (dict(cols=1), mpsim.MPS_E_INVAL), (dict(rows=0), mpsim.MPS_E_INVAL),
     (dict(cols=9), mpsim.MPS_E_UNSUPPORTED), (dict(chi=0), mpsim.MPS_E_INVAL),
-    (dict(order=3), mpsim.MPS_E_INVAL), (dict(schedule=2), mpsim.MPS_E_UNSUPPORTED)])
+    (dict(order=3), mpsim.MPS_E_INVAL), (dict(schedule=3), mpsim.MPS_E_INVAL)])
 def test_invalid_config_rejected(kw, status):
     args = dict(rows=4, cols=4, chi=16)
     args.update(kw)

@@ -162,6 +162,36 @@ def test_t4_full_bond_dimension_is_exact(R, C, chi, steps, order):
         assert np.all(ref[k:] < 1e-10) and np.all(got[k:] < 1e-10)
 
 
+@pytest.mark.parametrize("R,C,chi,steps,order", [(3, 3, 64, 4, 1), (4, 4, 256, 3, 1),
+                                                  (3, 4, 64, 3, 2), (5, 2, 32, 4, 1)])
+def test_t4_rotating_schedule_full_chi_is_exact(R, C, chi, steps, order):
+    """The rotating-row schedule applies every coupling once per step: at full
+    bond dimension it reproduces the exact Trotterised state."""
+    g = Grid(R, C)
+    m = mps.BlockMPS(g, chi, 0.6, J, H, DT, order, schedule=2)
+    sv = statevector.StateVector(g, 0.6, J, H, DT, order)
+    for _ in range(steps):
+        m.step()
+        sv.step()
+        a, b = m.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < 1e-10 and abs(a["z2"] - b["z2"]) < 1e-10
+    assert abs(abs(np.vdot(sv.psi, m.to_statevector())) ** 2 - 1) < 1e-10
+
+
+@pytest.mark.parametrize("R,C", [(3, 3), (4, 4), (5, 6), (6, 8), (7, 8), (5, 5), (3, 2)])
+def test_rotating_schedule_gates_each_pair_once(R, C):
+    g = Grid(R, C)
+    pos = g.snake()
+    coupled = {frozenset((a, b)) for a in range(g.n_blocks)
+               for b in range(a + 1, g.n_blocks) if pair_coupled(g, a, b)}
+    for _ in range(2 * R):
+        ops = step_ops(g, pos, 1, 2)
+        gated = [frozenset((o[4], o[5])) for o in ops if o[0] == "U2" and o[3]]
+        assert len(gated) == len(set(gated)) and set(gated) == coupled
+    nu2 = sum(1 for o in ops if o[0] == "U2")
+    assert nu2 == (7 * R - 8 if R % 2 == 0 else 7 * R - 7)
+
+
 def test_t4_translation_invariance_full_chi():
     g = Grid(3, 4)
     m = mps.BlockMPS(g, 64, 0.5, J, H, DT)
