@@ -137,6 +137,39 @@ def served(time_limit: float, chi_cap: int, n_req: int, seed: int = 2511) -> dic
     return out
 
 
+def concurrent(rows: int, cols: int, chi: int, precision: str, schedule: int, count: int,
+               seed: int) -> dict:
+    """`count` independent instances of the workload (distinct seeded random
+    start states at saturated bonds), each on its own stream, stepped
+    together through the batched entry point; one step and one measurement
+    per instance in the timed region."""
+    import torch
+    from paper_2511_23438_amd import mpsim, workloads
+    sims, streams = [], []
+    for k in range(count):
+        st = torch.cuda.Stream()
+        cfg = mpsim.make_config(rows, cols, chi, precision=precision, schedule=schedule)
+        with torch.cuda.stream(st):
+            sim = mpsim.Simulation(cfg, stream=st.cuda_stream)
+        sites, centre = workloads.random_mps(rows, cols, chi, seed + 1 + k, centre=rows - 1)
+        sim.set_state(sites, centre)
+        del sites
+        sims.append(sim)
+        streams.append(st)
+        log("concurrent instance %d loaded" % k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mpsim.apply_batched(sims, 1)
+    obs = [s.measure() for s in sims]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for s in sims:
+        s.free()
+    return {"instances": count, "seconds": el, "steps_per_s": count / el,
+            "per_instance_steps_per_s": 1.0 / el,
+            "z": [o["z"] for o in obs], "fidelity": [o["fidelity"] for o in obs]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +193,8 @@ def main() -> int:
                     help="admission window of the served run (0 disables it)")
     ap.add_argument("--serve-chi-cap", type=int, default=32)
     ap.add_argument("--serve-requests", type=int, default=8)
+    ap.add_argument("--instances", type=int, default=0,
+                    help="also time this many concurrent instances of the workload")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -269,6 +304,11 @@ def main() -> int:
         log("served: %s" % {k: out["served"][k] for k in ("completed", "steps_per_s",
                                                          "step_latency_ms_p50",
                                                          "step_latency_ms_p99")})
+    if args.instances > 0:
+        log("concurrent run: %d instances" % args.instances)
+        out["concurrent"] = concurrent(args.rows, args.cols, args.chi, args.precision,
+                                       args.schedule, args.instances, args.seed)
+        log("concurrent: %.3f steps/s aggregate" % out["concurrent"]["steps_per_s"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget,
                                            args.schedule)

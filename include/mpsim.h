@@ -69,6 +69,9 @@ typedef struct {
   void (*free)(void* ctx, void* ptr, void* stream);
 } mps_allocator;
 
+/* Gram side from which eig_path 0 takes the two-stage eigensolver. */
+#define MPS_EIG2_MIN 2048
+
 typedef struct {
   int32_t rows, cols;      /* R x C; rows >= 1, 2 <= cols <= 8 (block width <= 4, d <= 16) */
   int32_t chi_max;         /* maximum bond dimension, >= 1 */
@@ -77,7 +80,9 @@ typedef struct {
   int32_t schedule;        /* 1: wrap pairs routed by SWAPs and back (11R-12 updates/step);
                               2: rotating rows (7R-8 / 7R-7 updates/step, even / odd R) */
   int32_t periodic;        /* 1: periodic in both directions (the paper's TFIM); 0: open */
-  int32_t reserved;        /* must be 0 */
+  int32_t eig_path;        /* truncation eigensolver: 0 automatic (two-stage from a Gram
+                              side of MPS_EIG2_MIN on), 1 one-stage Householder
+                              tridiagonalisation, 2 two-stage (dense -> band -> tridiagonal) */
   double J, h, dt;         /* couplings and time step of eq. "hamiltonian" */
   double theta0;           /* absolute angle of eq. "initial_state" */
   uint64_t seed;           /* seeds the start vectors of the eigensolver (deterministic) */
@@ -180,9 +185,12 @@ mps_status mps_truncation_log(mps_handle h, double* f, double* gap, int32_t cap,
  * qubit q = r*C + c at bit n-1-q of the index. Synchronises. */
 mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len);
 
-/* Apply nsteps to each of `count` handles, interleaving their updates so the
- * device overlaps independent instances (each handle keeps its own stream).
- * Results equal applying the steps to each handle alone. */
+/* Apply nsteps to each of `count` distinct handles: one host thread per
+ * handle enqueues its steps on the handle's own stream, so the device runs
+ * independent instances concurrently. Results equal applying the steps to
+ * each handle alone. Returns when every step is enqueued (not completed);
+ * MPS_E_INVAL for a NULL or repeated handle, otherwise the first failing
+ * handle's status (each handle records its own error). */
 mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t nsteps);
 
 /* Optional progress callback: called on the host after each two-site update

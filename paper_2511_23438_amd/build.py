@@ -11,11 +11,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpsim.so")
-SOURCES = ["gemm.hip", "linalg.hip", "mps_kernels.hip", "planner.cpp", "mpsim.cpp"]
+SOURCES = ["gemm.hip", "linalg.hip", "band.hip", "mps_kernels.hip", "planner.cpp", "mpsim.cpp"]
 ARCH = os.environ.get("MPSIM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-pthread",
     # keep hipcc from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

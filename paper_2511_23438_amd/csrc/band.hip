@@ -1,0 +1,503 @@
+// Two-stage path to the top-q eigenspace of a Hermitian matrix (float64).
+//
+//   1. Dense -> band of half-width HB: for every panel of HB columns, a
+//      Householder QR of the block below the band and the two-sided update
+//      of the trailing matrix, A22 <- Q^H A22 Q = A22 - V W^H - W V^H with
+//      W = A22 V T - 1/2 V T^H V^H A22 V T. The products run on MFMA GEMMs
+//      (A22 V reads the stored lower triangle as a Hermitian operand), so the
+//      trailing matrix is read a few times per panel instead of once per
+//      column as in the one-stage reduction.
+//   2. Band -> real tridiagonal by bulge chasing, eigenvalues only. Sweep j
+//      removes column j below the subdiagonal and chases the bulge down in
+//      steps of HB rows. Each step touches a window of at most 2HB x 2HB
+//      entries; sweep j+1 runs three steps behind sweep j, which keeps the
+//      windows of one time slot disjoint, so one launch per time slot runs
+//      all of its steps as independent workgroups.
+//   3. Eigenvalues of the tridiagonal by bisection (shared with the one-stage
+//      path).
+//   4. Eigenvectors of the band matrix by inverse iteration: band LU with
+//      partial pivoting of B - lambda I (one wave per vector, the active
+//      window in LDS), back substitution, two iterations; then Householder QR
+//      of the vectors (only the spanned subspace matters) and the stage-1
+//      block reflectors applied in reverse order.
+#include "linalg.h"
+
+#include <algorithm>
+#include <cfloat>
+
+namespace mpsim {
+
+constexpr int HB = TRD_NB;        // band half-width
+constexpr int ABW = 2 * HB + 1;   // stored sub-diagonal offsets per band column
+constexpr int URW = 2 * HB + 2;   // stored U row: 2HB+1 entries and the RHS value
+
+static_assert(HB == 32, "the band kernels assume a half-width of 32");
+
+// ---------------------------------------------------------------------------
+// Stage 1
+
+// Band of the reduced matrix: Ab[j*ABW + o] = A[j + o, j] for o <= HB, zero
+// for the offsets that fill-in may reach later; diagonal made real.
+__global__ void k_band_extract(int n, const cplx* A, long lda, cplx* Ab) {
+  const long total = (long)n * ABW;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long j = idx / ABW;
+    const int o = (int)(idx % ABW);
+    cplx v = make_double2(0.0, 0.0);
+    if (o <= HB && j + o < n) {
+      v = A[j * lda + j + o];
+      if (o == 0) v.y = 0.0;
+    }
+    Ab[idx] = v;
+  }
+}
+
+void he2hb_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
+  const cplx one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  for (int p = 0, i0 = 0; i0 + HB < n - 1; ++p, i0 += HB) {
+    const int o = i0 + HB;
+    const int m = n - o;
+    const int kb = std::min(HB, m);
+    cplx* T = w.T1 + (long)p * 4096;
+    cplx* A22 = A + (long)o * lda + o;
+    // panel QR; leaves the explicit V (m x kb, column-major ld vmax) in w.V
+    LinalgWork wp = w;
+    wp.T = T;
+    qr_factor(m, HB, A + (long)i0 * lda + o, 1, lda, wp, s);
+    // X = A22 V (row-major, ld 64)
+    ZGemm gx = zgemm_args(m, kb, m, zop(A22, lda, 1), zop(w.V, w.vmax, 1), w.X2, 64, 0, one, zero);
+    gx.herm_a = 1;
+    zgemm(gx, w.gpart, w.gpart_elems, s, w.prof);
+    // Y = X T (column-major, ld nmax, in w.W)
+    ZGemm gy = zgemm_args(m, kb, kb, zop(w.X2, 64, 0), zop(T, 64, 0), w.W, w.nmax, 1, one, zero);
+    zgemm(gy, nullptr, 0, s, w.prof);
+    // S = V^H Y, Z = T^H S
+    ZGemm gs = zgemm_args(kb, kb, m, zop(w.V, w.vmax, 0, 1), zop(w.W, w.nmax, 1), w.S, 64, 0, one,
+                          zero);
+    zgemm(gs, w.gpart, w.gpart_elems, s, w.prof);
+    ZGemm gz = zgemm_args(kb, kb, kb, zop(T, 64, 1, 1), zop(w.S, 64, 0), w.S2, 64, 0, one, zero);
+    zgemm(gz, nullptr, 0, s, w.prof);
+    // W = Y - 1/2 V Z (in place)
+    ZGemm gw = zgemm_args(m, kb, kb, zop(w.V, w.vmax, 1), zop(w.S2, 64, 0), w.W, w.nmax, 1,
+                          make_double2(-0.5, 0.0), one);
+    zgemm(gw, nullptr, 0, s, w.prof);
+    // A22 -= [V W] [W V]^H on the lower triangle
+    ZGemm g1 = zgemm_args(m, m, 2 * kb, zop(w.V, w.vmax, 1), zop(w.W, w.nmax, 0, 1), A22, lda, 1,
+                          make_double2(-1.0, 0.0), one);
+    g1.kcat = kb;
+    g1.A2 = zop(w.W, w.nmax, 1);
+    g1.B2 = zop(w.V, w.vmax, 0, 1);
+    g1.lower_only = 1;
+    zgemm(g1, nullptr, 0, s, w.prof);
+  }
+}
+
+// X (n x q row-major) <- Q1 X, Q1 the product of the stage-1 panel reflectors
+// (stored below the band of A, block factors in w.T1).
+void he2hb_backtransform(int n, const cplx* A, long lda, int q, cplx* X, long ldx, LinalgWork& w,
+                         hipStream_t s) {
+  int np = 0;
+  for (int i0 = 0; i0 + HB < n - 1; i0 += HB) ++np;
+  for (int p = np - 1; p >= 0; --p) {
+    const int i0 = p * HB, o = i0 + HB, m = n - o;
+    const int kb = std::min(HB, m);
+    extract_v(A, 1, lda, o, i0, m, kb, w.V, w.vmax, s);
+    apply_block_reflector(m, q, kb, w.T1 + (long)p * 4096, 0, X + (long)o * ldx, ldx, 1, w, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: bulge chasing on the band (lower storage Ab[col*ABW + row - col])
+
+__device__ inline int hb_steps(int n, int j) { return (n - 1 - j + HB - 1) / HB; }
+
+// One step of sweep j = jlo + blockIdx.x at time slot `slot` (step k =
+// slot - 3j): reflector from column c, rows r..r+L-1; applied from the left
+// to rows R = [r, r+L) of columns c+1..r-1, from both sides to the diagonal
+// block R x R, and from the right to rows [r+L, r+L+Lb) of columns R.
+__global__ __launch_bounds__(256) void k_hb2st(int n, cplx* Ab, int slot, int jlo) {
+  const int j = jlo + blockIdx.x;
+  if (j > n - 3) return;
+  const int k = slot - 3 * j;
+  if (k < 0 || k >= hb_steps(n, j)) return;
+  const int r = j + 1 + k * HB;
+  const int c = (k == 0) ? j : r - HB;
+  const int L = min(HB, n - r);
+  if (L < 2) return;
+  const int Lb = min(HB, n - r - L);
+  const int nl = r - c - 1;
+  __shared__ cplx Bl[HB][HB + 1];
+  __shared__ cplx D[HB][HB + 1];
+  __shared__ cplx Bb[HB][HB + 1];
+  __shared__ cplx x[HB], v[HB], pv[HB], qv[HB], wl[HB], wv[HB];
+  __shared__ double sc[8];
+  const int t = threadIdx.x;
+#define AB(row, col) Ab[(long)(col) * ABW + ((row) - (col))]
+  // all loads of the three blocks are issued before any is waited for
+#pragma unroll
+  for (int e = t; e < HB * HB; e += 256) {
+    const int i = e % HB, jj = e / HB;
+    if (i < L && jj < nl) Bl[i][jj] = AB(r + i, c + 1 + jj);
+    if (i < L && jj < L && i >= jj) {
+      cplx dv = AB(r + i, r + jj);
+      if (i == jj) dv.y = 0.0;
+      D[i][jj] = dv;
+    }
+    if (i < Lb && jj < L) Bb[i][jj] = AB(r + L + i, r + jj);
+  }
+  if (t < L) x[t] = AB(r + t, c);
+  __syncthreads();
+  for (int e = t; e < HB * HB; e += 256) {
+    const int i = e % HB, jj = e / HB;
+    if (i < L && jj < L && i < jj) D[i][jj] = cconj(D[jj][i]);
+  }
+  if (t < 64) {
+    double xn = (t >= 1 && t < L) ? cabs2(x[t]) : 0.0;
+    xn = wave_sum(xn);
+    if (t == 0) {
+      double beta;
+      cplx tau, scl;
+      reflector(x[0], xn, beta, tau, scl);
+      sc[0] = beta; sc[1] = tau.x; sc[2] = tau.y; sc[3] = scl.x; sc[4] = scl.y;
+    }
+  }
+  __syncthreads();
+  const cplx tau = make_double2(sc[1], sc[2]);
+  if (t < L) v[t] = (t == 0) ? make_double2(1.0, 0.0) : cmul(x[t], make_double2(sc[3], sc[4]));
+  __syncthreads();
+  if (t < 64) {
+    if (t < nl) {
+      cplx acc = make_double2(0.0, 0.0);
+      for (int i = 0; i < L; ++i) acc = cadd(acc, cmulc(v[i], Bl[i][t]));
+      wl[t] = acc;
+    }
+  } else if (t < 128) {
+    const int i = t - 64;
+    if (i < L) {
+      cplx acc = make_double2(0.0, 0.0);
+      for (int jj = 0; jj < L; ++jj) acc = cadd(acc, cmul(D[i][jj], v[jj]));
+      pv[i] = acc;
+    }
+  } else if (t < 192) {
+    const int i = t - 128;
+    if (i < Lb) {
+      cplx acc = make_double2(0.0, 0.0);
+      for (int jj = 0; jj < L; ++jj) acc = cadd(acc, cmul(Bb[i][jj], v[jj]));
+      qv[i] = acc;
+    }
+  }
+  __syncthreads();
+  if (t < 64) {
+    // v^H p is real (Hermitian block)
+    double sre = (t < L) ? cmulc(v[t], pv[t]).x : 0.0;
+    sre = wave_sum(sre);
+    if (t == 0) sc[5] = sre;
+  }
+  __syncthreads();
+  if (t < L) {
+    const double at2 = cabs2(tau);
+    wv[t] = csub(cmul(tau, pv[t]), cscale(v[t], 0.5 * at2 * sc[5]));
+  }
+  __syncthreads();
+  const cplx ctau = cconj(tau);
+  for (int e = t; e < HB * HB; e += 256) {
+    const int i = e % HB, jj = e / HB;
+    if (i < L && jj < nl) Bl[i][jj] = csub(Bl[i][jj], cmul(ctau, cmul(v[i], wl[jj])));
+    if (i < L && jj < L && i >= jj) {
+      cplx dv = csub(D[i][jj], cadd(cmul(wv[i], cconj(v[jj])), cmul(v[i], cconj(wv[jj]))));
+      if (i == jj) dv.y = 0.0;
+      D[i][jj] = dv;
+    }
+    if (i < Lb && jj < L) Bb[i][jj] = csub(Bb[i][jj], cmul(tau, cmul(qv[i], cconj(v[jj]))));
+  }
+  __syncthreads();
+  for (int e = t; e < HB * HB; e += 256) {
+    const int i = e % HB, jj = e / HB;
+    if (i < L && jj < nl) AB(r + i, c + 1 + jj) = Bl[i][jj];
+    if (i < L && jj < L && i >= jj) AB(r + i, r + jj) = D[i][jj];
+    if (i < Lb && jj < L) AB(r + L + i, r + jj) = Bb[i][jj];
+  }
+  if (t < L) AB(r + t, c) = (t == 0) ? make_double2(sc[0], 0.0) : make_double2(0.0, 0.0);
+#undef AB
+}
+
+__global__ void k_hb_tridiag(int n, const cplx* Ab, double* d, double* e) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    d[i] = Ab[(long)i * ABW].x;
+    if (i < n - 1) e[i] = sqrt(cabs2(Ab[(long)i * ABW + 1]));
+  }
+}
+
+void hb2st(int n, cplx* Ab, LinalgWork& w, hipStream_t s) {
+  if (n >= 3) {
+    const int st0 = (n - 1 + HB - 1) / HB;  // steps of sweep 0 (the most)
+    int nslots = 0;
+    for (int j = 0; j <= n - 3; ++j) nslots = std::max(nslots, 3 * j + (n - 1 - j + HB - 1) / HB);
+    for (int slot = 0; slot < nslots; ++slot) {
+      const int jhi = std::min(n - 3, slot / 3);
+      const int jlo = std::max(0, (slot - st0 + 1 + 2) / 3);
+      if (jhi < jlo) continue;
+      hipLaunchKernelGGL(k_hb2st, dim3(jhi - jlo + 1), dim3(256), 0, s, n, Ab, slot, jlo);
+    }
+  }
+  hipLaunchKernelGGL(k_hb_tridiag, dim3(std::max(1, std::min(ceil_div(n, 256), 1024))), dim3(256), 0,
+                     s, n, (const cplx*)Ab, w.d, w.e);
+}
+
+// ---------------------------------------------------------------------------
+// Band inverse iteration
+
+// Row-major copy of the Hermitian band: Br[i*ABW + o] = B[i, i - HB + o].
+__global__ void k_band_rows(int n, const cplx* Ab, cplx* Br) {
+  const long total = (long)n * ABW;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long i = idx / ABW;
+    const int o = (int)(idx % ABW);
+    const long jc = i - HB + o;
+    cplx v = make_double2(0.0, 0.0);
+    if (jc >= 0 && jc < n) {
+      if (jc <= i) v = Ab[jc * ABW + (i - jc)];
+      else v = cconj(Ab[i * ABW + (jc - i)]);
+    }
+    Br[idx] = v;
+  }
+}
+
+__device__ inline double band_hash(uint64_t seed, uint64_t a, uint64_t b) {
+  uint64_t z = seed ^ (a * 0x9E3779B97F4A7C15ULL) ^ (b * 0xC2B2AE3D27D4EB4FULL);
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+}
+
+constexpr int WR = HB + 1;        // window rows
+constexpr int WC = 2 * HB + 1;    // window columns
+constexpr int CH = 4;             // rows staged per chunk (LDS: 4 waves per CU)
+
+// One wave per eigenvector (vector index v0 + blockIdx.x, column kq of X for
+// the kq-th largest eigenvalue). Window W[row % WR][col % WC] holds rows
+// k..k+HB and columns k..k+2HB of the partially eliminated B - lambda I.
+__global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q, const double* lam,
+                                                  int lam_off, const double* bounds, cplx* Ubuf,
+                                                  int v0, cplx* X, long ldx, uint64_t seed,
+                                                  int iters) {
+  __shared__ cplx Wn[WR][WC];
+  __shared__ cplx yv[WR];
+  __shared__ cplx lb[HB];
+  __shared__ cplx stage[CH][URW];
+  const int kq = v0 + blockIdx.x;
+  if (kq >= q) return;
+  const int l = threadIdx.x;
+  cplx* U = Ubuf + (long)blockIdx.x * n * URW;
+  const double lmb = lam[lam_off + q - 1 - kq];
+  double epsp = DBL_EPSILON * bounds[2];
+  if (epsp == 0.0) epsp = DBL_MIN;
+  for (int it = 0; it < iters; ++it) {
+    // ---- forward: LU with partial pivoting, RHS carried along
+    for (int e = l; e < WR * WC; e += 64) Wn[e / WC][e % WC] = make_double2(0.0, 0.0);
+    __syncthreads();
+    // rows 0..HB: B[i, jc] for jc in [0, 2HB] (Br offset o = jc - i + HB)
+    for (int e = l; e < WR * WC; e += 64) {
+      const int i = e / WC, jc = e % WC;
+      if (i < n && jc < n) {
+        const int o = jc - i + HB;
+        if (o >= 0 && o < ABW) {
+          cplx b = Br[(long)i * ABW + o];
+          if (o == HB) b.x -= lmb;
+          Wn[i % WR][jc % WC] = b;
+        }
+      }
+    }
+    if (l < WR && l < n) {
+      if (it == 0) yv[l] = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)l), 0.0);
+      else yv[l] = X[(long)l * ldx + kq];
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += CH) {
+      // stage the rows entering the window in this chunk: k0+WR .. k0+WR+CH-1
+      for (int e = l; e < CH * ABW; e += 64) {
+        const int rr = e / ABW, o = e % ABW;
+        const long i = (long)k0 + WR + rr;
+        cplx b = make_double2(0.0, 0.0);
+        if (i < n) {
+          b = Br[i * ABW + o];
+          if (o == HB) b.x -= lmb;
+        }
+        stage[rr][o] = b;
+      }
+      if (l < CH) {
+        const long i = (long)k0 + WR + l;
+        cplx y0 = make_double2(0.0, 0.0);
+        if (i < n) {
+          if (it == 0) y0 = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)i), 0.0);
+          else y0 = X[i * ldx + kq];
+        }
+        stage[l][ABW] = y0;
+      }
+      __syncthreads();
+      const int kend = min(n, k0 + CH);
+      for (int k = k0; k < kend; ++k) {
+        const int cs = k % WC;
+        // pivot: largest |W[i][k]| over rows k..min(n-1, k+HB)
+        double best = -1.0;
+        int bi = k;
+        if (l < WR && k + l < n) {
+          best = cabs2(Wn[(k + l) % WR][cs]);
+          bi = k + l;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        const int ks = k % WR;
+        if (bi != k) {
+          const int ps = bi % WR;
+          for (int cc = l; cc < WC; cc += 64) {
+            const cplx a = Wn[ks][cc];
+            Wn[ks][cc] = Wn[ps][cc];
+            Wn[ps][cc] = a;
+          }
+          if (l == 0) {
+            const cplx a = yv[ks];
+            yv[ks] = yv[ps];
+            yv[ps] = a;
+          }
+        }
+        __syncthreads();
+        cplx ukk = Wn[ks][cs];
+        if (cabs2(ukk) < epsp * epsp) ukk = make_double2(ukk.x < 0.0 ? -epsp : epsp, 0.0);
+        const cplx yk = yv[ks];
+        // U row k: offsets 0..2HB, then the eliminated RHS value
+        for (int o = l; o < WC; o += 64) U[(long)k * URW + o] = (o == 0) ? ukk : Wn[ks][(k + o) % WC];
+        if (l == 0) U[(long)k * URW + WC] = yk;
+        // multipliers of rows k+1..k+HB
+        if (l < HB) {
+          const int i = k + 1 + l;
+          cplx li = make_double2(0.0, 0.0);
+          if (i < n) li = cmul(Wn[i % WR][cs], cinv(ukk));
+          lb[l] = li;
+          if (i < n) yv[i % WR] = csub(yv[i % WR], cmul(li, yk));
+        }
+        __syncthreads();
+        {
+          // lane l updates column k+1+l of rows k+1..k+HB
+          const int cl = (k + 1 + l) % WC;
+          const cplx u = Wn[ks][cl];
+#pragma unroll 8
+          for (int tt = 0; tt < HB; ++tt) {
+            if (k + 1 + tt < n) {
+              cplx& wv = Wn[(k + 1 + tt) % WR][cl];
+              wv = csub(wv, cmul(lb[tt], u));
+            }
+          }
+        }
+        __syncthreads();
+        // advance: row k+WR takes row k's slot, column k+WC takes column k's
+        {
+          const int ni = k + WR;
+          const int rr = ni - (k0 + WR);   // its index in the staged chunk
+          for (int cc = l; cc < WC; cc += 64) {
+            // column index of slot cc in the new window [k+1, k+WC]
+            const int jc = k + 1 + ((cc - (k + 1) % WC) + WC) % WC;
+            cplx b = make_double2(0.0, 0.0);
+            if (ni < n) {
+              const int o = jc - ni + HB;
+              if (o >= 0 && o < ABW) b = stage[rr][o];
+            }
+            Wn[ks][cc] = b;
+          }
+          // the entering column is zero in every other row
+          for (int i2 = l; i2 < WR; i2 += 64)
+            if (i2 != ks) Wn[i2][cs] = make_double2(0.0, 0.0);
+          if (l == 0) yv[ks] = (ni < n) ? stage[rr][ABW] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+      }
+    }
+    // ---- back substitution: lane l holds x[jc] for the jc = l (mod 64) in
+    // [k+1, k+64]; rows staged CH at a time from U
+    cplx xr = make_double2(0.0, 0.0);
+    double mx = 0.0;
+    for (int kb = n - 1; kb >= 0; kb -= CH) {
+      const int klo = max(0, kb - CH + 1);
+      for (int e = l; e < (kb - klo + 1) * URW; e += 64) {
+        const int rr = e / URW, o = e % URW;
+        stage[rr][o] = U[(long)(klo + rr) * URW + o];
+      }
+      __syncthreads();
+      for (int k = kb; k >= klo; --k) {
+        const int rr = k - klo;
+        const int o = ((l - (k + 1)) % 64 + 64) % 64 + 1;   // jc = k + o
+        cplx p = make_double2(0.0, 0.0);
+        if (k + o < n) p = cmul(stage[rr][o], xr);
+        p.x = wave_sum(p.x);
+        p.y = wave_sum(p.y);
+        const cplx xk = cmul(csub(stage[rr][WC], p), cinv(stage[rr][0]));
+        if (l == (k & 63)) xr = xk;
+        if (l == 0) {
+          X[(long)k * ldx + kq] = xk;
+          mx = fmax(mx, fmax(fabs(xk.x), fabs(xk.y)));
+        }
+      }
+      __syncthreads();
+    }
+    // normalise (the scale first, against overflow)
+    mx = __shfl(mx, 0, 64);
+    if (!(mx > 0.0) || !isfinite(mx)) mx = 1.0;
+    double s2 = 0.0;
+    for (int i = l; i < n; i += 64) {
+      const cplx a = X[(long)i * ldx + kq];
+      s2 += cabs2(make_double2(a.x / mx, a.y / mx));
+    }
+    s2 = wave_sum(s2);
+    double nrm = sqrt(s2);
+    if (!(nrm > 0.0)) nrm = 1.0;
+    const double scv = 1.0 / (mx * nrm);
+    for (int i = l; i < n; i += 64) {
+      const cplx a = X[(long)i * ldx + kq];
+      X[(long)i * ldx + kq] = make_double2(a.x * scv, a.y * scv);
+    }
+    __syncthreads();
+  }
+}
+
+// vectors per inverse-iteration launch (bounds the U workspace)
+int band_invit_batch(int q) { return std::min(q, 1024); }
+
+long band_invit_work_elems(long n, int q) { return (long)band_invit_batch(q) * n * URW; }
+
+void band_invit(int n, const cplx* Br, int q, int lam_off, LinalgWork& w, cplx* X, long ldx,
+                uint64_t seed, hipStream_t s) {
+  const int bs = band_invit_batch(q);
+  for (int v0 = 0; v0 < q; v0 += bs) {
+    const int cnt = std::min(bs, q - v0);
+    hipLaunchKernelGGL(k_band_invit, dim3(cnt), dim3(64), 0, s, n, Br, q, (const double*)w.lam,
+                       lam_off, (const double*)(w.scal + 8), w.Ubuf, v0, X, ldx, seed, 2);
+  }
+}
+
+void heev_top_2stage(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
+                     uint64_t seed, hipStream_t s) {
+  he2hb_lower(n, G, ldg, w, s);
+  const long tot = (long)n * ABW;
+  const int bl = (int)std::min<long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_band_extract, dim3(bl), dim3(256), 0, s, n, (const cplx*)G, ldg, w.Ab);
+  hipLaunchKernelGGL(k_band_rows, dim3(bl), dim3(256), 0, s, n, (const cplx*)w.Ab, w.Br);
+  hb2st(n, w.Ab, w, s);
+  const int extra = (q < n) ? 1 : 0;
+  tridiag_eigvals(n, n - q - extra, q + extra, w, s);
+  band_invit(n, w.Br, q, extra, w, Xtmp, q, seed, s);
+  qr_factor(n, q, Xtmp, q, 1, w, s);
+  qr_form_q(n, q, Xtmp, q, 1, w, U, ldu, s);
+  he2hb_backtransform(n, G, ldg, q, U, ldu, w, s);
+}
+
+}  // namespace mpsim

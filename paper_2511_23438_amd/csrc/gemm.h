@@ -39,6 +39,10 @@ struct ZGemm {
   // and B2 (k - kcat, j); A2/B2 share the trans and conj flags of A/B
   int kcat;
   ZOp A2, B2;
+  // herm_a: op(A) is the M x M Hermitian matrix whose lower triangle is
+  // stored column-major at A.p (ld A.ld); A.trans / A.conj are ignored.
+  // Float64 only, row-major C, no second K segment.
+  int herm_a;
 };
 
 // C = alpha*op(A)*op(B) + beta*C (or the theta epilogue). `partial` is a

@@ -53,10 +53,44 @@ __device__ inline cplx elem_b(const ZGemm& g, const cplx* B, long gk, long gj) {
   return TB == 0 ? P[gk * ld + gj] : P[gj * ld + gk];
 }
 
+// Hermitian operand with the lower triangle stored column-major: which
+// lane layout a K-tile is loaded with. 0: the tile lies in the upper triangle
+// (read the stored transpose, 4 consecutive k per thread); 1: otherwise (4
+// consecutive i per thread; on tiles that cross the diagonal each element is
+// picked from the lower or the mirrored position).
+__device__ inline int herm_tile_lower(int m0, long k0) { return k0 < (long)m0 + BM; }
+
 template <int TA>
 __device__ inline void load_a(const ZGemm& g, const cplx* A, int m0, long k0, long kend,
                               cplx r[4]) {
   int t = threadIdx.x;
+  if (TA == 2) {
+    const long ld = g.A.ld;
+    if (!herm_tile_lower(m0, k0)) {
+      int i = t >> 2, kk = (t & 3) * 4;
+      long gi = m0 + i;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        long gk = k0 + kk + u;
+        r[u] = (gi < g.M && gk < kend) ? cconj(A[gi * ld + gk]) : make_double2(0, 0);
+      }
+    } else {
+      int k = t >> 4, ii = (t & 15) * 4;
+      long gk = k0 + k;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        long gi = m0 + ii + u;
+        cplx v = make_double2(0, 0);
+        if (gi < g.M && gk < kend) {
+          if (gi > gk) v = A[gk * ld + gi];
+          else if (gi < gk) v = cconj(A[gi * ld + gk]);
+          else v = make_double2(A[gk * ld + gi].x, 0.0);
+        }
+        r[u] = v;
+      }
+    }
+    return;
+  }
   if (TA == 0) {  // (i,k) at A[i*ld + k]: 4 consecutive k per thread
     int i = t >> 2, kk = (t & 3) * 4;
     long gi = m0 + i;
@@ -100,10 +134,10 @@ __device__ inline void load_b(const ZGemm& g, const cplx* B, int n0, long k0, lo
 }
 
 template <int TA>
-__device__ inline void store_a(double (*As)[BK][BM], const cplx r[4], int conj) {
+__device__ inline void store_a(double (*As)[BK][BM], const cplx r[4], int conj, int tile_lower = 1) {
   int t = threadIdx.x;
   double sg = conj ? -1.0 : 1.0;
-  if (TA == 0) {
+  if (TA == 0 || (TA == 2 && !tile_lower)) {
     int i = t >> 2, kk = (t & 3) * 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u) { As[0][kk + u][i] = r[u].x; As[1][kk + u][i] = sg * r[u].y; }
@@ -190,7 +224,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
   }
   for (long k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
-    store_a<TA>(As, ra, g.A.conj);
+    store_a<TA>(As, ra, TA == 2 ? 0 : g.A.conj, TA == 2 ? herm_tile_lower(m0, k0) : 1);
     store_b<TB>(Bs, rb, g.B.conj);
     __syncthreads();
     if (k0 + BK < kend) {
@@ -518,6 +552,13 @@ __global__ void zgemm_reduce(ZGemmDev gd) {
 void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Prof* prof) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return;
   ZGemm g = g0;
+  if (g.herm_a) {
+    // only the plain float64 product with a row-major result
+    g.prec = GEMM_F64;
+    g.kcat = 0;
+    g.transC = 0;
+    g.K = g.M;
+  }
   if (g.transC && g.epi == EPI_STORE) {
     // A column-major result is stored as C^T = op(B)^T op(A)^T, row-major,
     // so that neighbouring lanes write neighbouring addresses.
@@ -546,9 +587,12 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(256), 0, s, z);
     return;
   }
+  // split-K for skinny outputs; the Hermitian product (a few column tiles
+  // over a long K) is split until about 1024 workgroups run
+  const long want = g.herm_a ? 1024 : 256;
   if (partial && g.epi == EPI_STORE && !g.lower_only && !g.upper_only && !g.kcat &&
-      tiles < 128 && g.K >= 1024) {
-    int ks = (int)std::min<long>(g.K / 256, (256 + tiles - 1) / tiles);
+      (tiles < 128 || g.herm_a) && g.K >= 1024) {
+    int ks = (int)std::min<long>(g.K / 256, (want + tiles - 1) / tiles);
     while (ks > 1 && (long)ks * g.batch * g.M * g.N > partial_elems) --ks;
     if (ks > 1) {
       gd.ksplit = ks;
@@ -569,7 +613,10 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     else if (ta == 1 && tb == 0) hipLaunchKernelGGL((KER<1, 0>), grid, dim3(256), 0, s, gd); \
     else hipLaunchKernelGGL((KER<1, 1>), grid, dim3(256), 0, s, gd);                         \
   } while (0)
-  if (g.prec == GEMM_F32) MPS_GEMM_DISPATCH(cgemm_f32_kernel);
+  if (g.herm_a) {
+    if (tb == 0) hipLaunchKernelGGL((zgemm_kernel<2, 0>), grid, dim3(256), 0, s, gd);
+    else hipLaunchKernelGGL((zgemm_kernel<2, 1>), grid, dim3(256), 0, s, gd);
+  } else if (g.prec == GEMM_F32) MPS_GEMM_DISPATCH(cgemm_f32_kernel);
   else if (g.prec == GEMM_BF16X3) MPS_GEMM_DISPATCH(cgemm_bf16x3_kernel);
   else MPS_GEMM_DISPATCH(zgemm_kernel);
 #undef MPS_GEMM_DISPATCH

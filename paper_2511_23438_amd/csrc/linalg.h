@@ -10,6 +10,22 @@ namespace mpsim {
 
 constexpr int TRD_NB = 32, QR_NB = 32, BT_NB = 64;
 
+// Reflector H = I - tau v v^H with v = [1; x*scale] such that
+// H^H [alpha; x] = [beta; 0], beta real.
+__device__ inline void reflector(cplx alpha, double xnorm2, double& beta, cplx& tau, cplx& scale) {
+  if (xnorm2 == 0.0 && alpha.y == 0.0) {
+    beta = alpha.x;
+    tau = make_double2(0.0, 0.0);
+    scale = make_double2(0.0, 0.0);
+    return;
+  }
+  double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+  beta = (alpha.x >= 0.0) ? -nrm : nrm;
+  tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+  scale = cinv(make_double2(alpha.x - beta, alpha.y));
+}
+
+
 struct LinalgWork {
   long nmax = 0, qmax = 0, mmax = 0;  // eig dim, wanted count, QR rows
   cplx* W = nullptr;        // nmax x TRD_NB (col-major, ld nmax)
@@ -41,6 +57,13 @@ struct LinalgWork {
   cplx* gpart = nullptr;    // split-K partials
   long gpart_elems = 0;
   int* flag = nullptr;      // numeric failure flag (device)
+  // two-stage path
+  cplx* T1 = nullptr;       // stage-1 panel block factors, (nmax/TRD_NB + 1) * 4096
+  cplx* X2 = nullptr;       // nmax x 64 (row-major)
+  cplx* S2 = nullptr;       // 64 x 64
+  cplx* Ab = nullptr;       // band, nmax x (2*TRD_NB + 1), bulge-chased in place
+  cplx* Br = nullptr;       // row-major copy of the band before chasing
+  cplx* Ubuf = nullptr;     // inverse-iteration U rows, band_invit_work_elems()
   Prof* prof = nullptr;     // optional launch timing
 };
 
@@ -73,6 +96,25 @@ void qr_form_q(int m, int k, const cplx* A, long rs, long cs, LinalgWork& w, cpl
                hipStream_t s);
 // R (kmin x k row-major, ld ldr) from a factored matrix.
 void qr_get_r(int m, int k, const cplx* A, long rs, long cs, cplx* R, long ldr, hipStream_t s);
+
+// Block reflectors (compact WY): V from the reflectors stored at
+// A[(row0 + r)*rs + (col0 + j)*cs] into w.V, T into `T` (64 x 64 row-major);
+// C <- (I - V op(T) V^H) C with op(T) = T or T^H (tconj).
+void extract_v(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib, cplx* V,
+               long ldv, hipStream_t s);
+void block_reflector(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib,
+                     const cplx* tau, cplx* T, LinalgWork& w, hipStream_t s);
+void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, int tconj, cplx* C, long rs,
+                           long cs, LinalgWork& w, hipStream_t s);
+
+// Two-stage path (band.hip): dense -> band (half-width TRD_NB) by panel QR
+// and two-sided MFMA updates, band -> tridiagonal by bulge chasing
+// (eigenvalues), inverse iteration on the band, QR, back-transformation.
+// Same contract as heev_top.
+void heev_top_2stage(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
+                     uint64_t seed, hipStream_t s);
+long band_invit_work_elems(long n, int q);
+constexpr int BAND_W = 2 * TRD_NB + 1;
 
 // Top-q eigenspace of Hermitian G (n x n column-major, overwritten): an
 // orthonormal basis U (n x q row-major, ld ldu) ordered by descending

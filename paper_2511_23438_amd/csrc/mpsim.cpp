@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mpsim.h"
@@ -30,6 +31,7 @@ struct mps_sim {
   mps_config cfg{};
   Plan plan;
   hipStream_t stream = nullptr;
+  int device = 0;
   mps_allocator alloc{};
   bool has_alloc = false;
   std::vector<void*> allocations;
@@ -110,10 +112,12 @@ T* dalloc(mps_sim* h, long count) {
 struct Sizes {
   long site_max = 0, sites_total = 0, theta = 0, gram = 0, nmax = 1, qmax = 1, mmax = 1,
        colmax = 1, tmp = 0, env = 0, envx = 0;
+  int eig_path = 0;
 };
 
 Sizes plan_sizes(const Plan& p) {
   Sizes z;
+  z.eig_path = p.eig_path;
   const long D = p.dmax;
   for (int s = 0; s < p.N; ++s) {
     long e = (long)p.cap[s] * D * p.cap[s + 1];
@@ -133,6 +137,8 @@ Sizes plan_sizes(const Plan& p) {
   // bond spectrum Gram (cap x cap) also fits: cap <= kg bound
   z.mmax = std::max(z.mmax, z.nmax);
   z.colmax = std::max(z.colmax, z.qmax);
+  // the two-stage panels factor TRD_NB columns at a time
+  z.colmax = std::max<long>(z.colmax, TRD_NB);
   z.tmp = std::max(z.site_max, z.nmax * z.qmax);
   long cmax = 1;
   for (int s = 0; s <= p.N; ++s) cmax = std::max(cmax, (long)p.cap[s]);
@@ -143,7 +149,13 @@ Sizes plan_sizes(const Plan& p) {
 
 struct LwSizes {
   long W, tpart, P, dpart, npart, iwork, T, V, W12, gpart;
+  long T1, X2, band, ubuf;  // two-stage path (zero when it is never taken)
 };
+
+// whether a Gram side of n takes the two-stage eigensolver
+static bool use_two_stage(int eig_path, long n) {
+  return eig_path == 2 || (eig_path == 0 && n >= MPS_EIG2_MIN);
+}
 
 LwSizes lw_sizes(const Sizes& z) {
   LwSizes l;
@@ -159,6 +171,13 @@ LwSizes lw_sizes(const Sizes& z) {
   l.V = std::max(z.nmax, z.mmax) * 64;
   l.W12 = 64 * z.colmax;
   l.gpart = 4L << 20;
+  l.T1 = l.X2 = l.band = l.ubuf = 0;
+  if (use_two_stage(z.eig_path, z.nmax)) {
+    l.T1 = (z.nmax / TRD_NB + 2) * 4096;
+    l.X2 = z.nmax * 64;
+    l.band = z.nmax * BAND_W;
+    l.ubuf = band_invit_work_elems(z.nmax, (int)z.qmax);
+  }
   return l;
 }
 
@@ -170,6 +189,7 @@ size_t footprint(const Plan& p) {
   total += (size_t)z.sites_total * c;
   total += (size_t)(z.theta + z.gram + 3 * z.tmp + 2 * z.env + z.envx) * c;
   total += (size_t)(l.W + l.tpart + l.P + l.dpart + l.T + 4096 + 2 * l.W12 + l.V + l.gpart) * c;
+  total += (size_t)(l.T1 + l.X2 + 4096 + 2 * l.band + l.ubuf) * c;
   total += (size_t)(l.npart + l.iwork + 4 * z.nmax + z.qmax + 2 + 16 + 2 * 4096) * d;
   total += (size_t)(z.nmax + z.colmax) * c;
   return total;
@@ -266,6 +286,14 @@ void move_centre(mps_sim* h, int target) {
 // (and SWAP) fused into the GEMM epilogue, then truncation to
 // q = min(chi, rows, cols) through the top-q eigenspace of the Gram matrix on
 // the smaller side, fidelity bookkeeping and renormalisation.
+// Top-q eigenspace of the Gram matrix (kg x kg in h->gram) into U (kg x q).
+void heev(mps_sim* h, int kg, int q, cplx* U, uint64_t seed) {
+  if (use_two_stage(h->plan.eig_path, kg))
+    heev_top_2stage(kg, h->gram, kg, q, U, q, h->tmpA, h->lw, seed, h->stream);
+  else
+    heev_top(kg, h->gram, kg, q, U, q, h->tmpA, h->lw, seed, h->stream);
+}
+
 void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   const Plan& p = h->plan;
   if (h->centre < i) move_centre(h, i);
@@ -309,7 +337,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     gg.lower_only = 1;
     gg.tag = PROF_GRAM;
     zgemm(gg, nullptr, 0, s, &h->prof);
-    heev_top(kg, h->gram, kg, q, h->site[i], q, h->tmpA, h->lw, seed, s);
+    heev(h, kg, q, h->site[i], seed);
     // C = U^H M -> site i+1 (q x no)
     ZGemm gc = zgemm_args(q, (int)no, kg, zop(h->site[i], q, 1, 1), zop(h->theta, no, 0), h->site[i + 1],
                           no, 0, one, zero);
@@ -328,7 +356,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     gg.lower_only = 1;
     gg.tag = PROF_GRAM;
     zgemm(gg, nullptr, 0, s, &h->prof);
-    heev_top(kg, h->gram, kg, q, h->tmpB, q, h->tmpA, h->lw, seed, s);
+    heev(h, kg, q, h->tmpB, seed);
     launch_conj_transpose(h->tmpB, kg, q, q, h->site[i + 1], kg, s);
     // C = M V -> site i (mo x q)
     ZGemm gc = zgemm_args((int)mo, q, kg, zop(h->theta, no, 0), zop(h->tmpB, q, 0), h->site[i], q, 0, one,
@@ -501,6 +529,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
   mps_sim* h = new mps_sim();
   h->cfg = *cfg;
   h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   h->gprec = cfg->precision == MPS_C64_FP32ACC ? GEMM_F32
            : cfg->precision == MPS_BF16X3_FP32ACC ? GEMM_BF16X3 : GEMM_F64;
   if (alloc) {
@@ -557,6 +586,14 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     w.gpart_elems = l.gpart;
     w.flag = dalloc<int>(h, 4);
     w.prof = &h->prof;
+    if (l.T1) {
+      w.T1 = dalloc<cplx>(h, l.T1);
+      w.X2 = dalloc<cplx>(h, l.X2);
+      w.S2 = dalloc<cplx>(h, 4096);
+      w.Ab = dalloc<cplx>(h, l.band);
+      w.Br = dalloc<cplx>(h, l.band);
+      w.Ubuf = dalloc<cplx>(h, l.ubuf);
+    }
     // gate tables
     long off = 0;
     for (auto& t : p.pair_phase) { h->pair_off.push_back(off); off += (long)t.size(); }
@@ -632,12 +669,31 @@ mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t
   for (int k = 0; k < count; ++k) {
     if (!hs[k]) return fail(nullptr, MPS_E_INVAL, "NULL handle in batch");
     if (hs[k]->failed) return fail(hs[k], MPS_E_STATE, "handle has failed");
+    for (int k2 = 0; k2 < k; ++k2)
+      if (hs[k2] == hs[k]) return fail(nullptr, MPS_E_INVAL, "handle repeated in batch");
   }
-  for (int st = 0; st < nsteps; ++st)
-    for (int k = 0; k < count; ++k) {
-      mps_sim* h = hs[k];
-      TRYDEV(h, run_step(h); HIPCHK(hipGetLastError()));
+  // One host thread per instance, each enqueueing on its instance's own
+  // stream: a single thread would block on one instance's full launch queue
+  // while the other instances' queues drain.
+  std::vector<mps_status> st(count, MPS_OK);
+  auto run = [&](int k) {
+    mps_sim* h = hs[k];
+    if (hipSetDevice(h->device) != hipSuccess) {
+      st[k] = fail(h, MPS_E_DEVICE, "hipSetDevice failed");
+      return;
     }
+    st[k] = mps_apply_trotter_step(h, nsteps);
+  };
+  if (count == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    th.reserve(count);
+    for (int k = 0; k < count; ++k) th.emplace_back(run, k);
+    for (auto& t : th) t.join();
+  }
+  for (int k = 0; k < count; ++k)
+    if (st[k] != MPS_OK) return st[k];
   return MPS_OK;
 }
 

@@ -25,7 +25,7 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   if (cfg->trotter_order != 1 && cfg->trotter_order != 2) { *msg = "trotter_order must be 1 or 2"; return MPS_E_INVAL; }
   if (cfg->schedule != 1 && cfg->schedule != 2) { *msg = "schedule must be 1 or 2"; return MPS_E_INVAL; }
   if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
-  if (cfg->reserved != 0) { *msg = "reserved must be 0"; return MPS_E_INVAL; }
+  if (cfg->eig_path < 0 || cfg->eig_path > 2) { *msg = "eig_path must be 0, 1 or 2"; return MPS_E_INVAL; }
   if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
       !std::isfinite(cfg->theta0)) { *msg = "non-finite parameter"; return MPS_E_INVAL; }
   *msg = "";
@@ -93,6 +93,7 @@ void build_plan(const mps_config* cfg, Plan& p) {
   p.R = cfg->rows; p.C = cfg->cols; p.n = p.R * p.C; p.N = 2 * p.R;
   p.chi = cfg->chi_max; p.order = cfg->trotter_order; p.periodic = cfg->periodic;
   p.schedule = cfg->schedule;
+  p.eig_path = cfg->eig_path;
   p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
   p.wL = (p.C + 1) / 2; p.wR = p.C / 2;
   p.dmax = 1 << p.wL;

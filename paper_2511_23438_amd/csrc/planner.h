@@ -22,7 +22,7 @@ struct Op {          // one entry of the step schedule
 
 struct Plan {
   int R = 0, C = 0, n = 0, N = 0;  // grid, qubits, sites
-  int chi = 0, order = 1, periodic = 1, schedule = 1;
+  int chi = 0, order = 1, periodic = 1, schedule = 1, eig_path = 0;
   double J = 0, h = 0, dt = 0, theta0 = 0;
   int wL = 0, wR = 0, dmax = 1;
   std::vector<int> block_width;               // per block id

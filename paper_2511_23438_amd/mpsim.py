@@ -41,7 +41,7 @@ STATUS_NAME = {0: "MPS_OK", -1: "MPS_E_INVAL", -2: "MPS_E_NOMEM", -3: "MPS_E_DEV
 class MpsConfig(C.Structure):
     _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("chi_max", C.c_int32),
                 ("precision", C.c_int32), ("trotter_order", C.c_int32),
-                ("schedule", C.c_int32), ("periodic", C.c_int32), ("reserved", C.c_int32),
+                ("schedule", C.c_int32), ("periodic", C.c_int32), ("eig_path", C.c_int32),
                 ("J", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("theta0", C.c_double), ("seed", C.c_uint64)]
 
@@ -119,15 +119,15 @@ def _check(st: int, handle=None) -> None:
 def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
                 dt: float = 0.25, theta0: float = math.pi / 18, order: int = 1,
                 precision: str = "fp64", periodic: bool = True, seed: int = 0,
-                schedule: int = 1) -> MpsConfig:
+                schedule: int = 1, eig_path: int = 0) -> MpsConfig:
     return MpsConfig(rows, cols, chi, PRECISION[precision], order, schedule,
-                     1 if periodic else 0, 0, J, h, dt, theta0, seed)
+                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed)
 
 
 def config_from_instance(inst, seed: int = 0) -> MpsConfig:
     return make_config(inst.rows, inst.cols, inst.chi, inst.J, inst.h, inst.dt,
                        inst.theta0, inst.order, inst.precision, True, seed,
-                       getattr(inst, "schedule", 1))
+                       getattr(inst, "schedule", 1), getattr(inst, "eig_path", 0))
 
 
 def footprint_bytes(cfg: MpsConfig) -> int:

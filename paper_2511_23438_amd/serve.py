@@ -102,11 +102,14 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0][1].arrival_s - now)))
                 continue
             # one step for every active instance, all enqueued before any wait
+            evs = []
             for a in active:
                 ev0 = torch.cuda.Event(enable_timing=True)
-                ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record(a.stream)
-                a.sim.step(1)
+                evs.append(ev0)
+            mpsim.apply_batched([a.sim for a in active], 1)
+            for a, ev0 in zip(active, evs):
+                ev1 = torch.cuda.Event(enable_timing=True)
                 ev1.record(a.stream)
                 a.events.append((ev0, ev1))
                 a.steps_done += 1

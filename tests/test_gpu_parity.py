@@ -239,3 +239,65 @@ def test_rotating_schedule_truncating_parity(R, C, chi, steps, seed):
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
     assert sim.bond_dims() == ora.bond_dims()
     assert sim.site_blocks() == ora.pos
+
+
+@pytest.mark.parametrize("R,C,chi,steps", [(4, 4, 256, 2), (3, 4, 64, 3)])
+def test_two_stage_full_bond_dimension_matches_state_vector(R, C, chi, steps):
+    """Two-stage eigensolver (dense -> band -> tridiagonal, band inverse
+    iteration) forced for every truncation: still the exact Trotter state at
+    full bond dimension."""
+    g = Grid(R, C)
+    th = 0.6
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=th, eig_path=2))
+    sv = osv.StateVector(g, th, J, H, DT, 1)
+    for _ in range(steps):
+        sim.step(1)
+        sv.step()
+        a, b = sim.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["z2"] - b["z2"]) < TOL
+    psi = sim.to_statevector()
+    assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < TOL
+
+
+@pytest.mark.parametrize("R,C,chi,steps,seed", [(4, 4, 16, 3, 41), (5, 6, 64, 1, 42),
+                                                 (6, 8, 32, 1, 43), (3, 5, 24, 2, 44)])
+def test_two_stage_truncating_parity(R, C, chi, steps, seed):
+    """Two-stage eigensolver against the oracle's SVD truncation from a
+    symmetry-free start state (Gram sides up to 512: several stage-1 panels
+    and bulge-chasing sweeps)."""
+    sites, centre = workloads.random_mps(R, C, chi, seed)
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, eig_path=2))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(Grid(R, C), chi, sites, centre, J, H, DT)
+    for _ in range(steps):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        print(R, C, chi, "z err", abs(a["z"] - b["z"]), "logF err",
+              abs(a["log_fidelity"] - b["log_fidelity"]))
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL
+
+
+def test_one_and_two_stage_agree_on_wide_gram():
+    """Gram side 2048 (6x8, chi=128, bulk updates): both eigensolvers give
+    the same truncation (per-update f, observables) to the float64 bound."""
+    sites, centre = workloads.random_mps(6, 8, 128, 45, centre=5)
+    out = []
+    for path in (1, 2):
+        sim = mpsim.Simulation(mpsim.make_config(6, 8, 128, theta0=0.0, eig_path=path))
+        sim.set_state(sites, centre)
+        for (i, sw, gt) in [(5, 0, 1), (4, 1, 1), (6, 1, 1)]:
+            sim.apply_two_site(i, sw, gt)
+        f, _ = sim.truncation_log()
+        out.append((f, sim.measure()))
+        sim.free()
+    (f1, o1), (f2, o2) = out
+    print("f", f1, f2)
+    assert np.max(np.abs(f1 - f2)) < TOL
+    assert abs(o1["z"] - o2["z"]) < TOL and abs(o1["z2"] - o2["z2"]) < TOL
