@@ -28,108 +28,117 @@ struct ZGemmDev {
   cplx* partial;
 };
 
-// element (i, k) of op(A) before conjugation, with the optional second K segment
+// Operand loads are split in two: load_a / load_b only issue the loads, from
+// clamped (always valid) addresses and with the second K segment chosen by
+// selects, so no instruction between the prefetch and the multiplication of
+// the current tile needs the loaded values; fix_a / fix_b, called when the
+// tile is staged into LDS one step later, zero the out-of-range elements and
+// apply the Hermitian-operand mirroring.
+
+// address of element (i, k) of op(A) (before conjugation), with the
+// optional second K segment; (gi, gk) must be in range
 template <int TA>
-__device__ inline cplx elem_a(const ZGemm& g, const cplx* A, long gi, long gk) {
-  const cplx* P = A;
-  long ld = g.A.ld;
-  if (g.kcat && gk >= g.kcat) {
-    P = g.A2.p;
-    ld = g.A2.ld;
-    gk -= g.kcat;
-  }
-  return TA == 0 ? P[gi * ld + gk] : P[gk * ld + gi];
+__device__ inline const cplx* addr_a(const ZGemm& g, const cplx* A, long gi, long gk) {
+  const bool second = g.kcat && gk >= g.kcat;
+  const cplx* P = second ? g.A2.p : A;
+  const long ld = second ? g.A2.ld : g.A.ld;
+  const long k = second ? gk - g.kcat : gk;
+  return TA == 0 ? P + gi * ld + k : P + k * ld + gi;
 }
 
 template <int TB>
-__device__ inline cplx elem_b(const ZGemm& g, const cplx* B, long gk, long gj) {
-  const cplx* P = B;
-  long ld = g.B.ld;
-  if (g.kcat && gk >= g.kcat) {
-    P = g.B2.p;
-    ld = g.B2.ld;
-    gk -= g.kcat;
-  }
-  return TB == 0 ? P[gk * ld + gj] : P[gj * ld + gk];
+__device__ inline const cplx* addr_b(const ZGemm& g, const cplx* B, long gk, long gj) {
+  const bool second = g.kcat && gk >= g.kcat;
+  const cplx* P = second ? g.B2.p : B;
+  const long ld = second ? g.B2.ld : g.B.ld;
+  const long k = second ? gk - g.kcat : gk;
+  return TB == 0 ? P + k * ld + gj : P + gj * ld + k;
 }
 
 // Hermitian operand with the lower triangle stored column-major: which
 // lane layout a K-tile is loaded with. 0: the tile lies in the upper triangle
 // (read the stored transpose, 4 consecutive k per thread); 1: otherwise (4
 // consecutive i per thread; on tiles that cross the diagonal each element is
-// picked from the lower or the mirrored position).
+// read from the lower or the mirrored position).
 __device__ inline int herm_tile_lower(int m0, long k0) { return k0 < (long)m0 + BM; }
+
+// element coordinates handled by this thread for an A tile
+template <int TA>
+__device__ inline void coords_a(int m0, long k0, int u, long& gi, long& gk) {
+  const int t = threadIdx.x;
+  if (TA == 0 || (TA == 2 && !herm_tile_lower(m0, k0))) {
+    gi = m0 + (t >> 2);
+    gk = k0 + (t & 3) * 4 + u;
+  } else {
+    gk = k0 + (t >> 4);
+    gi = m0 + (t & 15) * 4 + u;
+  }
+}
 
 template <int TA>
 __device__ inline void load_a(const ZGemm& g, const cplx* A, int m0, long k0, long kend,
                               cplx r[4]) {
-  int t = threadIdx.x;
-  if (TA == 2) {
-    const long ld = g.A.ld;
-    if (!herm_tile_lower(m0, k0)) {
-      int i = t >> 2, kk = (t & 3) * 4;
-      long gi = m0 + i;
+  const long mlast = g.M - 1, klast = kend - 1;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        long gk = k0 + kk + u;
-        r[u] = (gi < g.M && gk < kend) ? cconj(A[gi * ld + gk]) : make_double2(0, 0);
-      }
+  for (int u = 0; u < 4; ++u) {
+    long gi, gk;
+    coords_a<TA>(m0, k0, u, gi, gk);
+    const long ci = min(gi, mlast), ck = min(gk, klast);
+    if (TA == 2) {
+      // stored lower element of (ci, ck) or of its mirror
+      r[u] = A[(ci >= ck) ? ck * g.A.ld + ci : ci * g.A.ld + ck];
     } else {
-      int k = t >> 4, ii = (t & 15) * 4;
-      long gk = k0 + k;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        long gi = m0 + ii + u;
-        cplx v = make_double2(0, 0);
-        if (gi < g.M && gk < kend) {
-          if (gi > gk) v = A[gk * ld + gi];
-          else if (gi < gk) v = cconj(A[gi * ld + gk]);
-          else v = make_double2(A[gk * ld + gi].x, 0.0);
-        }
-        r[u] = v;
-      }
+      r[u] = *addr_a<TA>(g, A, ci, ck);
     }
-    return;
   }
-  if (TA == 0) {  // (i,k) at A[i*ld + k]: 4 consecutive k per thread
-    int i = t >> 2, kk = (t & 3) * 4;
-    long gi = m0 + i;
+}
+
+template <int TA>
+__device__ inline void fix_a(const ZGemm& g, int m0, long k0, long kend, cplx r[4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      long gk = k0 + kk + u;
-      r[u] = (gi < g.M && gk < kend) ? elem_a<TA>(g, A, gi, gk) : make_double2(0, 0);
+  for (int u = 0; u < 4; ++u) {
+    long gi, gk;
+    coords_a<TA>(m0, k0, u, gi, gk);
+    cplx v = r[u];
+    if (TA == 2) {
+      if (gi < gk) v.y = -v.y;
+      if (gi == gk) v.y = 0.0;
     }
-  } else {        // (i,k) at A[k*ld + i]: 4 consecutive i per thread
-    int k = t >> 4, ii = (t & 15) * 4;
-    long gk = k0 + k;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      long gi = m0 + ii + u;
-      r[u] = (gi < g.M && gk < kend) ? elem_a<TA>(g, A, gi, gk) : make_double2(0, 0);
-    }
+    r[u] = (gi < g.M && gk < kend) ? v : make_double2(0.0, 0.0);
+  }
+}
+
+template <int TB>
+__device__ inline void coords_b(int n0, long k0, int u, long& gk, long& gj) {
+  const int t = threadIdx.x;
+  if (TB == 0) {
+    gk = k0 + (t >> 4);
+    gj = n0 + (t & 15) * 4 + u;
+  } else {
+    gj = n0 + (t >> 2);
+    gk = k0 + (t & 3) * 4 + u;
   }
 }
 
 template <int TB>
 __device__ inline void load_b(const ZGemm& g, const cplx* B, int n0, long k0, long kend,
                               cplx r[4]) {
-  int t = threadIdx.x;
-  if (TB == 0) {  // (k,j) at B[k*ld + j]: 4 consecutive j
-    int k = t >> 4, jj = (t & 15) * 4;
-    long gk = k0 + k;
+  const long nlast = g.N - 1, klast = kend - 1;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      long gj = n0 + jj + u;
-      r[u] = (gj < g.N && gk < kend) ? elem_b<TB>(g, B, gk, gj) : make_double2(0, 0);
-    }
-  } else {        // (k,j) at B[j*ld + k]: 4 consecutive k
-    int j = t >> 2, kk = (t & 3) * 4;
-    long gj = n0 + j;
+  for (int u = 0; u < 4; ++u) {
+    long gk, gj;
+    coords_b<TB>(n0, k0, u, gk, gj);
+    r[u] = *addr_b<TB>(g, B, min(gk, klast), min(gj, nlast));
+  }
+}
+
+template <int TB>
+__device__ inline void fix_b(const ZGemm& g, int n0, long k0, long kend, cplx r[4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      long gk = k0 + kk + u;
-      r[u] = (gj < g.N && gk < kend) ? elem_b<TB>(g, B, gk, gj) : make_double2(0, 0);
-    }
+  for (int u = 0; u < 4; ++u) {
+    long gk, gj;
+    coords_b<TB>(n0, k0, u, gk, gj);
+    r[u] = (gj < g.N && gk < kend) ? r[u] : make_double2(0.0, 0.0);
   }
 }
 
@@ -190,7 +199,10 @@ __device__ inline void store_out(const ZGemmDev& gd, int bz, int bat, long row, 
   C[idx] = out;
 }
 
-template <int TA, int TB>
+// WL selects the wave layout of the 64x64 tile: 0: 2x2 waves of 32x32;
+// 1: 4x1 waves of 16x32, for outputs at most 32 columns wide (no MFMA work
+// on columns past N).
+template <int TA, int TB, int WL = 0>
 __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
   const ZGemm& g = gd.g;
   __shared__ double As[2][BK][BM];
@@ -207,7 +219,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
   if (kend > g.K) kend = g.K;
 
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  constexpr int NA = WL ? 1 : 2;
+  const int wr = WL ? w * 16 : (w >> 1) * 32, wc = WL ? 0 : (w & 1) * 32;
   d4 cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -223,6 +236,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
     load_b<TB>(g, B, n0, kbeg, kend, rb);
   }
   for (long k0 = kbeg; k0 < kend; k0 += BK) {
+    fix_a<TA>(g, m0, k0, kend, ra);
+    fix_b<TB>(g, n0, k0, kend, rb);
     __syncthreads();
     store_a<TA>(As, ra, TA == 2 ? 0 : g.A.conj, TA == 2 ? herm_tile_lower(m0, k0) : 1);
     store_b<TB>(Bs, rb, g.B.conj);
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
       const int kr = kk * 4 + (l >> 4);
       double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < NA; ++a) {
         ar[a] = As[0][kr][wr + a * 16 + (l & 15)];
         ai[a] = As[1][kr][wr + a * 16 + (l & 15)];
       }
@@ -246,7 +261,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
         bi[b] = Bs[1][kr][wc + b * 16 + (l & 15)];
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
@@ -259,7 +274,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
 
   // epilogue (f64 result layout: register v of lane l is row 4v + l/16)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -340,6 +355,8 @@ __global__ __launch_bounds__(256) void cgemm_f32_kernel(ZGemmDev gd) {
   }
   for (long k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
+    fix_a<TA>(g, m0, k0, kend, ra);
+    fix_b<TB>(g, n0, k0, kend, rb);
     store_a_f32<TA>(As, ra, g.A.conj);
     store_b_f32<TB>(Bs, rb, g.B.conj);
     __syncthreads();
@@ -483,10 +500,14 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
     __syncthreads();
     load_a<TA>(g, A, m0, k0, kend, ra);
     load_b<TB>(g, B, n0, k0, kend, rb);
+    fix_a<TA>(g, m0, k0, kend, ra);
+    fix_b<TB>(g, n0, k0, kend, rb);
     stage_a_bf<TA>(As, ra, 0, g.A.conj);
     stage_b_bf<TB>(Bs, rb, 0, g.B.conj);
     load_a<TA>(g, A, m0, k0 + BK, kend, ra);
     load_b<TB>(g, B, n0, k0 + BK, kend, rb);
+    fix_a<TA>(g, m0, k0 + BK, kend, ra);
+    fix_b<TB>(g, n0, k0 + BK, kend, rb);
     stage_a_bf<TA>(As, ra, BK, g.A.conj);
     stage_b_bf<TB>(Bs, rb, BK, g.B.conj);
     __syncthreads();
@@ -613,9 +634,16 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     else if (ta == 1 && tb == 0) hipLaunchKernelGGL((KER<1, 0>), grid, dim3(256), 0, s, gd); \
     else hipLaunchKernelGGL((KER<1, 1>), grid, dim3(256), 0, s, gd);                         \
   } while (0)
+  const bool narrow = g.N <= 32 && g.epi == EPI_STORE;
   if (g.herm_a) {
-    if (tb == 0) hipLaunchKernelGGL((zgemm_kernel<2, 0>), grid, dim3(256), 0, s, gd);
+    if (narrow && tb == 1) hipLaunchKernelGGL((zgemm_kernel<2, 1, 1>), grid, dim3(256), 0, s, gd);
+    else if (tb == 0) hipLaunchKernelGGL((zgemm_kernel<2, 0>), grid, dim3(256), 0, s, gd);
     else hipLaunchKernelGGL((zgemm_kernel<2, 1>), grid, dim3(256), 0, s, gd);
+  } else if (narrow && g.prec == GEMM_F64) {
+    if (ta == 0 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<0, 0, 1>), grid, dim3(256), 0, s, gd);
+    else if (ta == 0 && tb == 1) hipLaunchKernelGGL((zgemm_kernel<0, 1, 1>), grid, dim3(256), 0, s, gd);
+    else if (ta == 1 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<1, 0, 1>), grid, dim3(256), 0, s, gd);
+    else hipLaunchKernelGGL((zgemm_kernel<1, 1, 1>), grid, dim3(256), 0, s, gd);
   } else if (g.prec == GEMM_F32) MPS_GEMM_DISPATCH(cgemm_f32_kernel);
   else if (g.prec == GEMM_BF16X3) MPS_GEMM_DISPATCH(cgemm_bf16x3_kernel);
   else MPS_GEMM_DISPATCH(zgemm_kernel);
