@@ -1,7 +1,10 @@
 // Complex float64 GEMM on gfx950 matrix cores.
 //
-// A complex product is four real products on v_mfma_f64_16x16x4f64:
-//   Cr += Ar*Br - Ai*Bi,  Ci += Ar*Bi + Ai*Br.
+// A complex product takes three real products on v_mfma_f64_16x16x4f64
+// (Gauss): with T1 = Ar*Br, T2 = Ai*Bi, T3 = (Ar + Ai)*(Br + Bi),
+//   Cr = T1 - T2,  Ci = T3 - T1 - T2;
+// the sums Ar + Ai and Br + Bi are formed once when a tile is staged in LDS
+// (a third plane). The reduced-precision kernels below use four products.
 // Tiles of 64x64 outputs per 256-thread workgroup (4 waves, 32x32 each as
 // 2x2 MFMA blocks), K staged through LDS 16 at a time with the real and
 // imaginary planes split (planar in LDS, interleaved in HBM), and the next
@@ -142,6 +145,7 @@ __device__ inline void fix_b(const ZGemm& g, int n0, long k0, long kend, cplx r[
   }
 }
 
+// planes: 0 real, 1 imaginary, 2 real + imaginary (after conjugation)
 template <int TA>
 __device__ inline void store_a(double (*As)[BK][BM], const cplx r[4], int conj, int tile_lower = 1) {
   int t = threadIdx.x;
@@ -149,11 +153,17 @@ __device__ inline void store_a(double (*As)[BK][BM], const cplx r[4], int conj, 
   if (TA == 0 || (TA == 2 && !tile_lower)) {
     int i = t >> 2, kk = (t & 3) * 4;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { As[0][kk + u][i] = r[u].x; As[1][kk + u][i] = sg * r[u].y; }
+    for (int u = 0; u < 4; ++u) {
+      const double re = r[u].x, im = sg * r[u].y;
+      As[0][kk + u][i] = re; As[1][kk + u][i] = im; As[2][kk + u][i] = re + im;
+    }
   } else {
     int k = t >> 4, ii = (t & 15) * 4;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { As[0][k][ii + u] = r[u].x; As[1][k][ii + u] = sg * r[u].y; }
+    for (int u = 0; u < 4; ++u) {
+      const double re = r[u].x, im = sg * r[u].y;
+      As[0][k][ii + u] = re; As[1][k][ii + u] = im; As[2][k][ii + u] = re + im;
+    }
   }
 }
 
@@ -164,11 +174,17 @@ __device__ inline void store_b(double (*Bs)[BK][BN], const cplx r[4], int conj) 
   if (TB == 0) {
     int k = t >> 4, jj = (t & 15) * 4;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { Bs[0][k][jj + u] = r[u].x; Bs[1][k][jj + u] = sg * r[u].y; }
+    for (int u = 0; u < 4; ++u) {
+      const double re = r[u].x, im = sg * r[u].y;
+      Bs[0][k][jj + u] = re; Bs[1][k][jj + u] = im; Bs[2][k][jj + u] = re + im;
+    }
   } else {
     int j = t >> 2, kk = (t & 3) * 4;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { Bs[0][kk + u][j] = r[u].x; Bs[1][kk + u][j] = sg * r[u].y; }
+    for (int u = 0; u < 4; ++u) {
+      const double re = r[u].x, im = sg * r[u].y;
+      Bs[0][kk + u][j] = re; Bs[1][kk + u][j] = im; Bs[2][kk + u][j] = re + im;
+    }
   }
 }
 
@@ -203,10 +219,10 @@ __device__ inline void store_out(const ZGemmDev& gd, int bz, int bat, long row, 
 // 1: 4x1 waves of 16x32, for outputs at most 32 columns wide (no MFMA work
 // on columns past N).
 template <int TA, int TB, int WL = 0>
-__global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
+__global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemmDev gd) {
   const ZGemm& g = gd.g;
-  __shared__ double As[2][BK][BM];
-  __shared__ double Bs[2][BK][BN];
+  __shared__ double As[3][BK][BM];
+  __shared__ double Bs[3][BK][BN];
   const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
   if (g.lower_only && n0 >= m0 + BM) return;
   if (g.upper_only && m0 >= n0 + BN) return;
@@ -221,13 +237,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   constexpr int NA = WL ? 1 : 2;
   const int wr = WL ? w * 16 : (w >> 1) * 32, wc = WL ? 0 : (w & 1) * 32;
-  d4 cr[2][2], ci[2][2];
+  d4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = (d4){0, 0, 0, 0};
-      ci[a][b] = (d4){0, 0, 0, 0};
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
     }
 
   cplx ra[4], rb[4];
@@ -249,25 +266,26 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (l >> 4);
-      double ar[2], ai[2], br[2], bi[2];
+      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         ar[a] = As[0][kr][wr + a * 16 + (l & 15)];
         ai[a] = As[1][kr][wr + a * 16 + (l & 15)];
+        as[a] = As[2][kr][wr + a * 16 + (l & 15)];
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         br[b] = Bs[0][kr][wc + b * 16 + (l & 15)];
         bi[b] = Bs[1][kr][wc + b * 16 + (l & 15)];
+        bs[b] = Bs[2][kr][wc + b * 16 + (l & 15)];
       }
 #pragma unroll
       for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+          t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], t1[a][b], 0, 0, 0);
+          t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], t2[a][b], 0, 0, 0);
+          t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[a], bs[b], t3[a][b], 0, 0, 0);
         }
     }
   }
@@ -280,7 +298,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmDev gd) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + wc + b * 16 + (l & 15),
-                  make_double2(cr[a][b][v], ci[a][b][v]));
+                  make_double2(t1[a][b][v] - t2[a][b][v],
+                               t3[a][b][v] - t1[a][b][v] - t2[a][b][v]));
 }
 
 
