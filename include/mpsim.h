@@ -218,6 +218,11 @@ typedef enum {
  * Diagnostic: adds two event records per timed launch. */
 mps_status mps_profile(mps_handle h, int32_t kind);
 
+/* Time only launches whose algorithmic work is at least min_work (>= 0;
+ * default 0, every launch of the class); takes effect with the next
+ * mps_profile call. */
+mps_status mps_profile_min_work(mps_handle h, double min_work);
+
 /* Accumulated device time (ms), number of timed launches and their
  * algorithmic work (bytes or flops, per the class). Synchronises. */
 mps_status mps_profile_read(mps_handle h, double* total_ms, int64_t* launches, double* work);

@@ -645,7 +645,7 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
   const int pk = (prof && prof->kind == PROF_GEMM) ? PROF_GEMM : g.tag;
   double flops = 8.0 * g.M * (double)g.N * g.K * g.batch;
   if (g.lower_only || g.upper_only) flops = 8.0 * g.M * (g.M + 1.0) * 0.5 * g.K * g.batch;
-  if (prof) prof->begin(pk, s);
+  if (prof) prof->begin(pk, flops, s);
 #define MPS_GEMM_DISPATCH(KER)                                                              \
   do {                                                                                      \
     if (ta == 0 && tb == 0) hipLaunchKernelGGL((KER<0, 0>), grid, dim3(256), 0, s, gd);     \

@@ -730,7 +730,7 @@ void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
       const long ntiles = (long)nt * (nt + 1) / 2;
       // at least 2j workgroups: each reduces some of the 2j column-step sums
       const unsigned grid = (unsigned)std::max<long>(std::min<long>(ntiles, HEMV_WGS), 2 * j);
-      if (w.prof) w.prof->begin(PROF_TRD_HEMV, s);
+      if (w.prof) w.prof->begin(PROF_TRD_HEMV, 16.0 * np * (np + 1.0) * 0.5, s);
 #if HEMV_VARIANT == 3
       hipLaunchKernelGGL(k_trd_hemv8, dim3(grid), dim3(512), 0, s, n, (const cplx*)A, lda, c, j,
                          (const cplx*)w.tpart, nb1, w.tsum, w.scal, w.d, w.e, w.tau, w.P, nt, ntiles);

@@ -917,6 +917,14 @@ mps_status mps_profile(mps_handle h, int32_t kind) {
   return MPS_OK;
 }
 
+mps_status mps_profile_min_work(mps_handle h, double min_work) {
+  GUARD(h);
+  if (!(min_work >= 0.0)) return fail(h, MPS_E_INVAL, "min_work must be >= 0");
+  h->prof.flush();
+  h->prof.min_work = min_work;
+  return MPS_OK;
+}
+
 mps_status mps_profile_read(mps_handle h, double* total_ms, int64_t* launches, double* work) {
   GUARD(h);
   if (!total_ms || !launches || !work) return fail(h, MPS_E_INVAL, "NULL output");

@@ -14,11 +14,12 @@ struct Prof {
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t used = 0;
   double ms = 0.0, work = 0.0;
+  double min_work = 0.0;  // launches with less algorithmic work are not timed
   long launches = 0;
 
-  bool on(int k) const { return kind != PROF_OFF && k == kind; }
-  void begin(int k, hipStream_t s) {
-    if (!on(k)) return;
+  bool on(int k, double w) const { return kind != PROF_OFF && k == kind && w >= min_work; }
+  void begin(int k, double w, hipStream_t s) {
+    if (!on(k, w)) return;
     if (2 * (used + 1) > ev.size()) {
       if (ev.size() < 8192) {
         size_t old = ev.size();
@@ -31,7 +32,7 @@ struct Prof {
     (void)hipEventRecord(ev[2 * used], s);
   }
   void end(int k, double w, hipStream_t s) {
-    if (!on(k)) return;
+    if (!on(k, w)) return;
     (void)hipEventRecord(ev[2 * used + 1], s);
     ++used;
     ++launches;

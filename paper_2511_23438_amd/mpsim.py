@@ -92,6 +92,7 @@ _sig = {
     "mps_sync": (C.c_int, [H]),
     "mps_set_progress": (C.c_int, [H, PROGRESS_FN, C.c_void_p]),
     "mps_profile": (C.c_int, [H, C.c_int32]),
+    "mps_profile_min_work": (C.c_int, [H, C.c_double]),
     "mps_profile_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
     "mps_last_error": (C.c_char_p, [H]),
@@ -244,7 +245,8 @@ class Simulation:
     # -- profiling ----------------------------------------------------------
     PROF = {"off": 0, "trd_hemv": 1, "gram": 2, "gemm": 3, "theta": 4}
 
-    def profile(self, kind: str) -> None:
+    def profile(self, kind: str, min_work: float = 0.0) -> None:
+        _check(_lib.mps_profile_min_work(self.h, float(min_work)), self.h)
         _check(_lib.mps_profile(self.h, self.PROF[kind]), self.h)
 
     def profile_read(self) -> tuple[float, int, float]:
