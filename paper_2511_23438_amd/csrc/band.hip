@@ -388,15 +388,25 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
         }
         __syncthreads();
         {
-          // lane l updates column k+1+l of rows k+1..k+HB
+          // lane l updates column k+1+l of rows k+1..k+HB, eight rows at a
+          // time: all reads of a group, then all writes (rows past n hold
+          // zeros and zero multipliers, so they are updated harmlessly)
           const int cl = (k + 1 + l) % WC;
           const cplx u = Wn[ks][cl];
-#pragma unroll 8
-          for (int tt = 0; tt < HB; ++tt) {
-            if (k + 1 + tt < n) {
-              cplx& wv = Wn[(k + 1 + tt) % WR][cl];
-              wv = csub(wv, cmul(lb[tt], u));
+          int slot = (k + 1) % WR;
+#pragma unroll
+          for (int g8 = 0; g8 < HB / 8; ++g8) {
+            cplx wv[8], lv[8];
+            int sl[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              sl[q] = slot;
+              slot = (slot + 1 == WR) ? 0 : slot + 1;
+              lv[q] = lb[g8 * 8 + q];
+              wv[q] = Wn[sl[q]][cl];
             }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Wn[sl[q]][cl] = csub(wv[q], cmul(lv[q], u));
           }
         }
         __syncthreads();

@@ -1069,46 +1069,20 @@ void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, int tcon
 // ---------------------------------------------------------------------------
 // Householder QR
 
-__global__ __launch_bounds__(256) void k_qr_norm(int m, const cplx* A, long rs, long cs, int c,
-                                                 double* npart) {
-  const long r = c + 1 + (long)blockIdx.x * 256 + threadIdx.x;
-  double v = (r < m) ? cabs2(A[r * rs + (long)c * cs]) : 0.0;
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) npart[(long)blockIdx.x * 4 + (threadIdx.x >> 6)] = v;
-}
+// Column steps of the panel factorisation, one launch per column. The
+// partial sums of column c (|x|^2 below the diagonal and the unscaled
+// products sum_r conj(A[r,c]) A[r,jj] for the later columns jj of the panel)
+// are reduced by every workgroup of the step; the reflector's scale is
+// applied to the reduced sums, so the dot products v^H A[:,jj] need no second
+// pass. The step then applies the reflector to its rows and forms the
+// partial sums of column c+1 from the updated values it holds.
+// Partial layout: part p = 4 * workgroup + wave; values 0..30 are the
+// products, 31 holds |x|^2.
 
-__global__ __launch_bounds__(256) void k_qr_dots(int m, const cplx* A, long rs, long cs, int c, int pe,
-                                                 const double* npart, int nnp, cplx* wpart,
-                                                 double* scal) {
-  __shared__ double sh[5];
-  __shared__ double bsh[4];
-  const int t = threadIdx.x;
-  double xn = 0.0;
-  for (int p = t; p < nnp; p += 256) xn += npart[p];
-  xn = block_sum(xn, bsh);
-  if (t == 0) {
-    double beta;
-    cplx tau, sc;
-    reflector(A[(long)c * rs + (long)c * cs], xn, beta, tau, sc);
-    sh[0] = beta; sh[1] = tau.x; sh[2] = tau.y; sh[3] = sc.x; sh[4] = sc.y;
-    if (blockIdx.x == 0)
-      for (int u = 0; u < 5; ++u) scal[u] = sh[u];
-  }
-  __syncthreads();
-  const cplx sc = make_double2(sh[3], sh[4]);
-  const long r = c + (long)blockIdx.x * 256 + t;
-  cplx v = make_double2(0.0, 0.0);
-  if (r < m) v = (r == c) ? make_double2(1.0, 0.0) : cmul(A[r * rs + (long)c * cs], sc);
-  // v^H A[:, jj] for jj = c+1 .. pe-1 (at most QR_NB - 1 values), reduced over
-  // the wave by a butterfly that halves the values held per lane (32 -> 1),
-  // then one plain exchange
-  cplx vals[QR_NB];
-#pragma unroll
-  for (int u = 0; u < QR_NB; ++u) {
-    const int jj = c + 1 + u;
-    vals[u] = (r < m && jj < pe) ? cmulc(v, A[r * rs + (long)jj * cs]) : make_double2(0.0, 0.0);
-  }
-  const int lane = t & 63;
+// butterfly over the 64 lanes of 32 complex values (halving the values held
+// per lane at each exchange), then one plain exchange; lane l with (l & 1) == 0
+// returns value b5*16 + b4*8 + b3*4 + b2*2 + b1 (bits of l)
+__device__ inline cplx qr_butterfly(cplx vals[QR_NB], int lane, int& vid) {
 #pragma unroll
   for (int half = QR_NB / 2, mm = 32; half >= 1; half >>= 1, mm >>= 1) {
     const bool upper = (lane & mm) != 0;
@@ -1125,70 +1099,117 @@ __global__ __launch_bounds__(256) void k_qr_dots(int m, const cplx* A, long rs, 
   cplx z = vals[0];
   z.x += __shfl_xor(z.x, 1, 64);
   z.y += __shfl_xor(z.y, 1, 64);
-  if ((lane & 1) == 0) {
-    const int vid = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-                    ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-    if (c + 1 + vid < pe) wpart[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + vid] = z;
-  }
+  vid = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+        ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+  return z;
 }
 
-__global__ __launch_bounds__(256) void k_qr_apply(int m, cplx* A, long rs, long cs, int c, int pe,
-                                                  const cplx* wpart, int nwp, const double* scal,
-                                                  double* npart, cplx* tau_out) {
+// partial sums of the first column c of a panel (rows c+1 .. m-1)
+__global__ __launch_bounds__(256) void k_qr_first(int m, const cplx* A, long rs, long cs, int c,
+                                                  int pe, cplx* part) {
+  const int t = threadIdx.x, lane = t & 63;
+  const long r = c + 1 + (long)blockIdx.x * 256 + t;
+  const bool in = r < m;
+  const cplx x = in ? A[r * rs + (long)c * cs] : make_double2(0.0, 0.0);
+  cplx vals[QR_NB];
+#pragma unroll
+  for (int u = 0; u < QR_NB - 1; ++u) {
+    const int jj = c + 1 + u;
+    vals[u] = (in && jj < pe) ? cmulc(x, A[r * rs + (long)jj * cs]) : make_double2(0.0, 0.0);
+  }
+  vals[QR_NB - 1] = make_double2(cabs2(x), 0.0);
+  int vid;
+  const cplx z = qr_butterfly(vals, lane, vid);
+  if ((lane & 1) == 0) part[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + vid] = z;
+}
+
+__global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs, int c, int pe,
+                                                const cplx* part, int nparts, cplx* part_next,
+                                                cplx* tau_out) {
+  __shared__ cplx red[8][QR_NB];
   __shared__ cplx wj[QR_NB];
-  __shared__ cplx wred[8][QR_NB];
-  const int t = threadIdx.x;
+  __shared__ double sh[5];
+  const int t = threadIdx.x, lane = t & 63;
+  const int ncol = pe - c - 1;  // later columns of the panel
   {
-    // column-step dot products: thread (g, jj) sums parts p = g, g + 8, ...
-    const int jj = t & (QR_NB - 1), g = t >> 5;
+    // reduce the partials: thread (g, u) sums parts g, g + 8, ...
+    const int u = t & (QR_NB - 1), g = t >> 5;
     cplx acc = make_double2(0.0, 0.0);
-    if (jj < pe - c - 1) {
+    if (u < ncol || u == QR_NB - 1) {
 #pragma unroll 4
-      for (int p = g; p < nwp; p += 8) acc = cadd(acc, wpart[(long)p * QR_NB + jj]);
+      for (int p = g; p < nparts; p += 8) acc = cadd(acc, part[(long)p * QR_NB + u]);
     }
-    wred[g][jj] = acc;
+    red[g][u] = acc;
   }
   __syncthreads();
-  if (t < pe - c - 1) {
-    cplx s = wred[0][t];
-    for (int g = 1; g < 8; ++g) s = cadd(s, wred[g][t]);
-    wj[t] = s;
+  if (t < QR_NB) {
+    cplx sum = red[0][t];
+    for (int g = 1; g < 8; ++g) sum = cadd(sum, red[g][t]);
+    red[0][t] = sum;
   }
   __syncthreads();
-  const double beta = scal[0];
-  const cplx tau = make_double2(scal[1], scal[2]), sc = make_double2(scal[3], scal[4]);
-  const cplx ctau = cconj(tau);
+  if (t == 0) {
+    double beta;
+    cplx tau, scl;
+    reflector(A[(long)c * rs + (long)c * cs], red[0][QR_NB - 1].x, beta, tau, scl);
+    sh[0] = beta; sh[1] = tau.x; sh[2] = tau.y; sh[3] = scl.x; sh[4] = scl.y;
+    if (blockIdx.x == 0) tau_out[c] = tau;
+  }
+  __syncthreads();
+  const cplx sc = make_double2(sh[3], sh[4]);
+  const cplx tau = make_double2(sh[1], sh[2]);
+  if (t < ncol)  // v^H A[:, jj] = A[c, jj] + conj(scale) * sum_r conj(A[r,c]) A[r,jj]
+    wj[t] = cadd(A[(long)c * rs + (long)(c + 1 + t) * cs], cmulc(sc, red[0][t]));
+  __syncthreads();
   const long r = c + (long)blockIdx.x * 256 + t;
-  double nn = 0.0;
-  if (r < m) {
-    const cplx v = (r == c) ? make_double2(1.0, 0.0) : cmul(A[r * rs + (long)c * cs], sc);
-    for (int jj = c + 1; jj < pe; ++jj) {
-      cplx a = csub(A[r * rs + (long)jj * cs], cmul(ctau, cmul(v, wj[jj - c - 1])));
-      A[r * rs + (long)jj * cs] = a;
-      if (jj == c + 1 && r >= c + 2) nn = cabs2(a);
-    }
-    A[r * rs + (long)c * cs] = (r == c) ? make_double2(beta, 0.0) : v;
+  const bool in = r < m;
+  cplx a[QR_NB - 1];
+  const cplx ctau = cconj(tau);
+  cplx v = make_double2(0.0, 0.0);
+  if (in) {
+    v = (r == c) ? make_double2(1.0, 0.0) : cmul(A[r * rs + (long)c * cs], sc);
+    A[r * rs + (long)c * cs] = (r == c) ? make_double2(sh[0], 0.0) : v;
   }
-  nn = wave_sum(nn);
-  if ((t & 63) == 0) npart[(long)blockIdx.x * 4 + (t >> 6)] = nn;
-  if (blockIdx.x == 0 && t == 0) tau_out[c] = tau;
+#pragma unroll
+  for (int u = 0; u < QR_NB - 1; ++u) {
+    const int jj = c + 1 + u;
+    cplx val = make_double2(0.0, 0.0);
+    if (in && jj < pe) {
+      val = csub(A[r * rs + (long)jj * cs], cmul(ctau, cmul(v, wj[u])));
+      A[r * rs + (long)jj * cs] = val;
+    }
+    a[u] = val;
+  }
+  if (c + 1 >= pe) return;
+  // partial sums of column c + 1 over rows c+2 .. m-1
+  const bool act = in && r >= c + 2;
+  const cplx x = act ? a[0] : make_double2(0.0, 0.0);
+  cplx vals[QR_NB];
+#pragma unroll
+  for (int u = 0; u < QR_NB - 1; ++u)
+    vals[u] = (u + 1 < QR_NB - 1) ? cmulc(x, a[u + 1 < QR_NB - 1 ? u + 1 : 0]) : make_double2(0.0, 0.0);
+  vals[QR_NB - 1] = make_double2(cabs2(x), 0.0);
+  int vid;
+  const cplx z = qr_butterfly(vals, lane, vid);
+  if ((lane & 1) == 0) part_next[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + vid] = z;
 }
 
 void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream_t s) {
   const int kmin = std::min(m, k);
-  cplx* wpart = w.tpart;
+  // two partial-sum buffers, alternating between column steps
+  cplx* partA = w.tpart;
+  cplx* partB = w.tpart + w.tpart_elems / 2;
   for (int p0 = 0, panel = 0; p0 < kmin; p0 += QR_NB, ++panel) {
     const int pe = std::min(p0 + QR_NB, kmin);
-    int nb0 = std::max(1, ceil_div(m - p0 - 1, 256));
-    hipLaunchKernelGGL(k_qr_norm, dim3(nb0), dim3(256), 0, s, m, (const cplx*)A, rs, cs, p0, w.npart);
-    int nnp = nb0 * 4;
+    const int nb0 = std::max(1, ceil_div(m - p0 - 1, 256));
+    hipLaunchKernelGGL(k_qr_first, dim3(nb0), dim3(256), 0, s, m, (const cplx*)A, rs, cs, p0, pe, partA);
+    int nparts = nb0 * 4;
     for (int c = p0; c < pe; ++c) {
       const int nbr = ceil_div(m - c, 256);
-      hipLaunchKernelGGL(k_qr_dots, dim3(nbr), dim3(256), 0, s, m, (const cplx*)A, rs, cs, c, pe,
-                         (const double*)w.npart, nnp, wpart, w.scal);
-      hipLaunchKernelGGL(k_qr_apply, dim3(nbr), dim3(256), 0, s, m, A, rs, cs, c, pe,
-                         (const cplx*)wpart, nbr * 4, (const double*)w.scal, w.npart, w.qtau);
-      nnp = nbr * 4;
+      hipLaunchKernelGGL(k_qr_col, dim3(nbr), dim3(256), 0, s, m, A, rs, cs, c, pe,
+                         (const cplx*)partA, nparts, partB, w.qtau);
+      std::swap(partA, partB);
+      nparts = nbr * 4;
     }
     const int ib = pe - p0;
     cplx* T = w.T + (long)panel * 4096;
