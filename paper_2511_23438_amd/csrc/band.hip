@@ -114,8 +114,11 @@ __device__ inline int hb_steps(int n, int j) { return (n - 1 - j + HB - 1) / HB;
 
 // One step of sweep j = jlo + blockIdx.x at time slot `slot` (step k =
 // slot - 3j): reflector from column c, rows r..r+L-1; applied from the left
-// to rows R = [r, r+L) of columns c+1..r-1, from both sides to the diagonal
-// block R x R, and from the right to rows [r+L, r+L+Lb) of columns R.
+// to rows R = [r, r+L) of columns c+1..r-1 (block Bl), from both sides to the
+// diagonal block R x R (D), and from the right to rows [r+L, r+L+Lb) of
+// columns R (Bb). Thread t keeps the elements (t % 32, t / 32 + 8 it) of the
+// three blocks in registers for the update; LDS holds copies for the
+// products, which 8-lane groups form in four-term pieces.
 __global__ __launch_bounds__(256) void k_hb2st(int n, cplx* Ab, int slot, int jlo) {
   const int j = jlo + blockIdx.x;
   if (j > n - 3) return;
@@ -130,93 +133,99 @@ __global__ __launch_bounds__(256) void k_hb2st(int n, cplx* Ab, int slot, int jl
   __shared__ cplx Bl[HB][HB + 1];
   __shared__ cplx D[HB][HB + 1];
   __shared__ cplx Bb[HB][HB + 1];
-  __shared__ cplx x[HB], v[HB], pv[HB], qv[HB], wl[HB], wv[HB];
+  __shared__ cplx x[HB], v[HB], pv[HB], qv[HB], wl[HB];
   __shared__ double sc[8];
-  const int t = threadIdx.x;
+  __shared__ double ssum[4];
+  const int t = threadIdx.x, lane = t & 63;
+  const int ri = t % HB, cj0 = t / HB;
 #define AB(row, col) Ab[(long)(col) * ABW + ((row) - (col))]
-  // all loads of the three blocks are issued before any is waited for
+  cplx rl[4], rd[4], rb[4];
 #pragma unroll
-  for (int e = t; e < HB * HB; e += 256) {
-    const int i = e % HB, jj = e / HB;
-    if (i < L && jj < nl) Bl[i][jj] = AB(r + i, c + 1 + jj);
-    if (i < L && jj < L && i >= jj) {
-      cplx dv = AB(r + i, r + jj);
-      if (i == jj) dv.y = 0.0;
-      D[i][jj] = dv;
+  for (int it = 0; it < 4; ++it) {
+    const int jj = cj0 + 8 * it;
+    rl[it] = (ri < L && jj < nl) ? AB(r + ri, c + 1 + jj) : make_double2(0.0, 0.0);
+    rd[it] = (ri < L && jj < L && ri >= jj) ? AB(r + ri, r + jj) : make_double2(0.0, 0.0);
+    rb[it] = (ri < Lb && jj < L) ? AB(r + L + ri, r + jj) : make_double2(0.0, 0.0);
+  }
+  if (t < HB) x[t] = (t < L) ? AB(r + t, c) : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int jj = cj0 + 8 * it;
+    Bl[ri][jj] = rl[it];
+    Bb[ri][jj] = rb[it];
+    if (ri == jj) rd[it].y = 0.0;
+    if (ri >= jj) {
+      D[ri][jj] = rd[it];
+      D[jj][ri] = cconj(rd[it]);
     }
-    if (i < Lb && jj < L) Bb[i][jj] = AB(r + L + i, r + jj);
   }
-  if (t < L) x[t] = AB(r + t, c);
   __syncthreads();
-  for (int e = t; e < HB * HB; e += 256) {
-    const int i = e % HB, jj = e / HB;
-    if (i < L && jj < L && i < jj) D[i][jj] = cconj(D[jj][i]);
-  }
   if (t < 64) {
+    // reflector; lanes 0..L-1 then form v
     double xn = (t >= 1 && t < L) ? cabs2(x[t]) : 0.0;
     xn = wave_sum(xn);
+    double beta = 0.0;
+    cplx tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
+    if (t == 0) reflector(x[0], xn, beta, tau, scl);
+    scl.x = __shfl(scl.x, 0, 64);
+    scl.y = __shfl(scl.y, 0, 64);
+    if (t < HB) v[t] = (t == 0) ? make_double2(1.0, 0.0) : (t < L ? cmul(x[t], scl) : make_double2(0.0, 0.0));
     if (t == 0) {
-      double beta;
-      cplx tau, scl;
-      reflector(x[0], xn, beta, tau, scl);
-      sc[0] = beta; sc[1] = tau.x; sc[2] = tau.y; sc[3] = scl.x; sc[4] = scl.y;
+      sc[0] = beta; sc[1] = tau.x; sc[2] = tau.y;
     }
+  }
+  __syncthreads();
+  {
+    // row / column q = t / 8 of the products, terms 4 (t % 8) .. 4 (t % 8) + 3
+    const int q = t >> 3, part = t & 7;
+    cplx pp = make_double2(0.0, 0.0), qq = pp, ww = pp;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int m = part * 4 + u;
+      const cplx vm = v[m];
+      pp = cadd(pp, cmul(D[q][m], vm));
+      qq = cadd(qq, cmul(Bb[q][m], vm));
+      ww = cadd(ww, cmulc(vm, Bl[m][q]));
+    }
+    // v^H D v (real): every piece of p times conj(v_q)
+    double sp = cmulc(v[q], pp).x;
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      pp.x += __shfl_xor(pp.x, off, 64);
+      pp.y += __shfl_xor(pp.y, off, 64);
+      qq.x += __shfl_xor(qq.x, off, 64);
+      qq.y += __shfl_xor(qq.y, off, 64);
+      ww.x += __shfl_xor(ww.x, off, 64);
+      ww.y += __shfl_xor(ww.y, off, 64);
+    }
+    if (part == 0) {
+      pv[q] = pp;
+      qv[q] = qq;
+      wl[q] = ww;
+    }
+    sp = wave_sum(sp);
+    if (lane == 0) ssum[t >> 6] = sp;
   }
   __syncthreads();
   const cplx tau = make_double2(sc[1], sc[2]);
-  if (t < L) v[t] = (t == 0) ? make_double2(1.0, 0.0) : cmul(x[t], make_double2(sc[3], sc[4]));
-  __syncthreads();
-  if (t < 64) {
-    if (t < nl) {
-      cplx acc = make_double2(0.0, 0.0);
-      for (int i = 0; i < L; ++i) acc = cadd(acc, cmulc(v[i], Bl[i][t]));
-      wl[t] = acc;
-    }
-  } else if (t < 128) {
-    const int i = t - 64;
-    if (i < L) {
-      cplx acc = make_double2(0.0, 0.0);
-      for (int jj = 0; jj < L; ++jj) acc = cadd(acc, cmul(D[i][jj], v[jj]));
-      pv[i] = acc;
-    }
-  } else if (t < 192) {
-    const int i = t - 128;
-    if (i < Lb) {
-      cplx acc = make_double2(0.0, 0.0);
-      for (int jj = 0; jj < L; ++jj) acc = cadd(acc, cmul(Bb[i][jj], v[jj]));
-      qv[i] = acc;
-    }
-  }
-  __syncthreads();
-  if (t < 64) {
-    // v^H p is real (Hermitian block)
-    double sre = (t < L) ? cmulc(v[t], pv[t]).x : 0.0;
-    sre = wave_sum(sre);
-    if (t == 0) sc[5] = sre;
-  }
-  __syncthreads();
-  if (t < L) {
-    const double at2 = cabs2(tau);
-    wv[t] = csub(cmul(tau, pv[t]), cscale(v[t], 0.5 * at2 * sc[5]));
-  }
-  __syncthreads();
   const cplx ctau = cconj(tau);
-  for (int e = t; e < HB * HB; e += 256) {
-    const int i = e % HB, jj = e / HB;
-    if (i < L && jj < nl) Bl[i][jj] = csub(Bl[i][jj], cmul(ctau, cmul(v[i], wl[jj])));
-    if (i < L && jj < L && i >= jj) {
-      cplx dv = csub(D[i][jj], cadd(cmul(wv[i], cconj(v[jj])), cmul(v[i], cconj(wv[jj]))));
-      if (i == jj) dv.y = 0.0;
-      D[i][jj] = dv;
+  const double hs = 0.5 * cabs2(tau) * (ssum[0] + ssum[1] + ssum[2] + ssum[3]);
+  // w = tau p - 1/2 |tau|^2 (v^H p) v
+  const cplx vi = v[ri];
+  const cplx wi = csub(cmul(tau, pv[ri]), cscale(vi, hs));
+  const cplx qi = qv[ri];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int jj = cj0 + 8 * it;
+    const cplx vj = v[jj];
+    if (ri < L && jj < nl) AB(r + ri, c + 1 + jj) = csub(rl[it], cmul(ctau, cmul(vi, wl[jj])));
+    if (ri < L && jj < L && ri >= jj) {
+      const cplx wj = csub(cmul(tau, pv[jj]), cscale(vj, hs));
+      cplx dv = csub(rd[it], cadd(cmul(wi, cconj(vj)), cmul(vi, cconj(wj))));
+      if (ri == jj) dv.y = 0.0;
+      AB(r + ri, r + jj) = dv;
     }
-    if (i < Lb && jj < L) Bb[i][jj] = csub(Bb[i][jj], cmul(tau, cmul(qv[i], cconj(v[jj]))));
-  }
-  __syncthreads();
-  for (int e = t; e < HB * HB; e += 256) {
-    const int i = e % HB, jj = e / HB;
-    if (i < L && jj < nl) AB(r + i, c + 1 + jj) = Bl[i][jj];
-    if (i < L && jj < L && i >= jj) AB(r + i, r + jj) = D[i][jj];
-    if (i < Lb && jj < L) AB(r + L + i, r + jj) = Bb[i][jj];
+    if (ri < Lb && jj < L) AB(r + L + ri, r + jj) = csub(rb[it], cmul(tau, cmul(qi, cconj(vj))));
   }
   if (t < L) AB(r + t, c) = (t == 0) ? make_double2(sc[0], 0.0) : make_double2(0.0, 0.0);
 #undef AB
