@@ -238,20 +238,73 @@ __global__ void k_hb_tridiag(int n, const cplx* Ab, double* d, double* e) {
   }
 }
 
+static void hb2st_launches(int n, cplx* Ab, hipStream_t s) {
+  if (n < 3) return;
+  const int st0 = (n - 1 + HB - 1) / HB;  // steps of sweep 0 (the most)
+  int nslots = 0;
+  for (int j = 0; j <= n - 3; ++j) nslots = std::max(nslots, 3 * j + (n - 1 - j + HB - 1) / HB);
+  for (int slot = 0; slot < nslots; ++slot) {
+    const int jhi = std::min(n - 3, slot / 3);
+    const int jlo = std::max(0, (slot - st0 + 1 + 2) / 3);
+    if (jhi < jlo) continue;
+    hipLaunchKernelGGL(k_hb2st, dim3(jhi - jlo + 1), dim3(256), 0, s, n, Ab, slot, jlo);
+  }
+}
+
+// The launch sequence depends only on n and the band's address, so it is
+// captured once into a HIP graph (on a private stream) and replayed; if
+// capture or instantiation fails the kernels are launched directly.
+static hipGraphExec_t hb2st_graph(int n, cplx* Ab, LinalgWork& w) {
+  for (auto& g : w.hbg)
+    if (g.exec && g.n == n && g.ab == Ab) return g.exec;
+  if (!w.cap_stream && hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    w.cap_stream = nullptr;
+    return nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(w.cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+  hb2st_launches(n, Ab, w.cap_stream);
+  if (hipStreamEndCapture(w.cap_stream, &graph) != hipSuccess || !graph) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  auto& slot = w.hbg[w.hbg_next];
+  w.hbg_next = (w.hbg_next + 1) % 2;
+  if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  if (slot.graph) (void)hipGraphDestroy(slot.graph);
+  slot.n = n;
+  slot.ab = Ab;
+  slot.graph = graph;
+  slot.exec = exec;
+  return exec;
+}
+
 void hb2st(int n, cplx* Ab, LinalgWork& w, hipStream_t s) {
   if (n >= 3) {
-    const int st0 = (n - 1 + HB - 1) / HB;  // steps of sweep 0 (the most)
-    int nslots = 0;
-    for (int j = 0; j <= n - 3; ++j) nslots = std::max(nslots, 3 * j + (n - 1 - j + HB - 1) / HB);
-    for (int slot = 0; slot < nslots; ++slot) {
-      const int jhi = std::min(n - 3, slot / 3);
-      const int jlo = std::max(0, (slot - st0 + 1 + 2) / 3);
-      if (jhi < jlo) continue;
-      hipLaunchKernelGGL(k_hb2st, dim3(jhi - jlo + 1), dim3(256), 0, s, n, Ab, slot, jlo);
+    hipGraphExec_t exec = hb2st_graph(n, Ab, w);
+    if (!exec || hipGraphLaunch(exec, s) != hipSuccess) {
+      (void)hipGetLastError();
+      hb2st_launches(n, Ab, s);
     }
   }
   hipLaunchKernelGGL(k_hb_tridiag, dim3(std::max(1, std::min(ceil_div(n, 256), 1024))), dim3(256), 0,
                      s, n, (const cplx*)Ab, w.d, w.e);
+}
+
+void linalg_release(LinalgWork& w) {
+  for (auto& g : w.hbg) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = LinalgWork::HbGraph{};
+  }
+  if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
+  w.cap_stream = nullptr;
 }
 
 // ---------------------------------------------------------------------------

@@ -64,6 +64,16 @@ struct LinalgWork {
   cplx* Ab = nullptr;       // band, nmax x (2*TRD_NB + 1), bulge-chased in place
   cplx* Br = nullptr;       // row-major copy of the band before chasing
   cplx* Ubuf = nullptr;     // inverse-iteration U rows, band_invit_work_elems()
+  // bulge-chasing launch sequences captured as HIP graphs, per (n, band)
+  struct HbGraph {
+    int n = -1;
+    const cplx* ab = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  HbGraph hbg[2];
+  int hbg_next = 0;
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
   Prof* prof = nullptr;     // optional launch timing
 };
 
@@ -114,6 +124,8 @@ void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, int tcon
 void heev_top_2stage(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
                      uint64_t seed, hipStream_t s);
 long band_invit_work_elems(long n, int q);
+// Destroys the captured graphs and the capture stream of `w`.
+void linalg_release(LinalgWork& w);
 constexpr int BAND_W = 2 * TRD_NB + 1;
 
 // Top-q eigenspace of Hermitian G (n x n column-major, overwritten): an

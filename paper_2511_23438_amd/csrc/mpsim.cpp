@@ -744,6 +744,7 @@ mps_status mps_fidelity(mps_handle h, double* fidelity, double* log_fidelity) {
 void mps_free(mps_handle h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  linalg_release(h->lw);
   for (void* p : h->allocations) {
     if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, (void*)h->stream);
     else (void)hipFree(p);
