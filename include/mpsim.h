@@ -73,12 +73,16 @@ typedef struct {
 #define MPS_EIG2_MIN 2048
 
 typedef struct {
-  int32_t rows, cols;      /* R x C; rows >= 1, 2 <= cols <= 8 (block width <= 4, d <= 16) */
+  int32_t rows, cols;      /* R x C; rows >= 1, 2 <= cols <= 8 (block width <= 4, d <= 16);
+                              with layers >= 2 the cube's first two extents (>= 1) */
   int32_t chi_max;         /* maximum bond dimension, >= 1 */
   int32_t precision;       /* mps_precision */
   int32_t trotter_order;   /* 1: exp(-i dt H_X) exp(-i dt H_ZZ); 2: eq. "trotter_step" */
   int32_t schedule;        /* 1: wrap pairs routed by SWAPs and back (11R-12 updates/step);
-                              2: rotating rows (7R-8 / 7R-7 updates/step, even / odd R) */
+                              2: rotating rows (7R-8 / 7R-7 updates/step, even / odd R);
+                              3: route and return, any lattice: each coupled block pair in
+                                 chain order, the far block swapped next to its partner,
+                                 gated, swapped back */
   int32_t periodic;        /* 1: periodic in both directions (the paper's TFIM); 0: open */
   int32_t eig_path;        /* truncation eigensolver: 0 automatic (two-stage from a Gram
                               side of MPS_EIG2_MIN on), 1 one-stage Householder
@@ -86,6 +90,10 @@ typedef struct {
   double J, h, dt;         /* couplings and time step of eq. "hamiltonian" */
   double theta0;           /* absolute angle of eq. "initial_state" */
   uint64_t seed;           /* seeds the start vectors of the eigensolver (deterministic) */
+  int32_t layers;          /* 0 or 1: the rows x cols grid above, half-row blocks. >= 2: the
+                              rows x cols x layers cubic lattice with one qubit per site
+                              (d = 2, snake through the cube; schedule must be 3) */
+  int32_t reserved;        /* must be 0 */
 } mps_config;
 
 typedef struct {

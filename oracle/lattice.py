@@ -59,6 +59,9 @@ class Grid:
     def block_dim(self, block: int) -> int:
         return 2 ** len(self.block_columns(block))
 
+    def block_width(self, block: int) -> int:
+        return len(self.block_columns(block))
+
     @property
     def n_blocks(self) -> int:
         return 2 * self.rows
@@ -108,6 +111,90 @@ class Grid:
         return m
 
 
+@dataclass(frozen=True)
+class Cube:
+    """Lx x Ly x Lz cubic lattice with one qubit per MPS site (local dimension
+    2), the three-dimensional generalisation in the paper's supplement (open
+    boundaries by default).
+
+    Qubit (x, y, z) has index q = (x*Ly + y)*Lz + z and is its own block.
+    Snake: x slowest; inside layer x the rows y run forward for even x and
+    backward for odd x; inside the t-th row visited (counting over all
+    layers) z runs forward for even t and backward for odd t. Consecutive
+    qubits of the snake are nearest neighbours.
+    """
+    lx: int
+    ly: int
+    lz: int
+    periodic: bool = False
+
+    @property
+    def n(self) -> int:
+        return self.lx * self.ly * self.lz
+
+    @property
+    def rows(self) -> int:
+        return self.lx
+
+    @property
+    def n_blocks(self) -> int:
+        return self.n
+
+    def qubit(self, x: int, y: int, z: int) -> int:
+        return (x * self.ly + y) * self.lz + z
+
+    def block_qubits(self, block: int) -> list[int]:
+        return [block]
+
+    def block_columns(self, block: int) -> list[int]:
+        return [0]
+
+    def block_width(self, block: int) -> int:
+        return 1
+
+    def block_dim(self, block: int) -> int:
+        return 2
+
+    def snake(self) -> list[int]:
+        pos = []
+        t = 0
+        for x in range(self.lx):
+            ys = range(self.ly) if x % 2 == 0 else range(self.ly - 1, -1, -1)
+            for y in ys:
+                zs = range(self.lz) if t % 2 == 0 else range(self.lz - 1, -1, -1)
+                for z in zs:
+                    pos.append(self.qubit(x, y, z))
+                t += 1
+        return pos
+
+    def zz_bonds(self) -> list[tuple[int, int]]:
+        seen = set()
+        out = []
+        dims = (self.lx, self.ly, self.lz)
+        for x in range(self.lx):
+            for y in range(self.ly):
+                for z in range(self.lz):
+                    c = (x, y, z)
+                    for ax in range(3):
+                        nb = list(c)
+                        nb[ax] += 1
+                        if nb[ax] >= dims[ax]:
+                            if not self.periodic or dims[ax] < 2:
+                                continue
+                            nb[ax] = 0
+                        a, b = self.qubit(*c), self.qubit(*nb)
+                        if a == b:
+                            continue
+                        key = (min(a, b), max(a, b))
+                        if key not in seen:
+                            seen.add(key)
+                            out.append(key)
+        return out
+
+    def block_of_qubit(self) -> dict[int, int]:
+        return {q: q for q in range(self.n)}
+
+
 def z_of(bits_index: int, w: int, j: int) -> int:
     """z eigenvalue (+1 for bit 0) of the j-th qubit of a w-qubit fused index,
     j = 0 being the most significant bit."""
@@ -115,9 +202,9 @@ def z_of(bits_index: int, w: int, j: int) -> int:
     return 1 - 2 * bit
 
 
-def block_z_values(grid: Grid, block: int) -> np.ndarray:
+def block_z_values(grid, block: int) -> np.ndarray:
     """z-array of shape (d, w): z of each qubit of the block for every s."""
-    w = len(grid.block_columns(block))
+    w = grid.block_width(block)
     d = 2 ** w
     out = np.empty((d, w), dtype=np.int64)
     for s in range(d):
@@ -126,7 +213,7 @@ def block_z_values(grid: Grid, block: int) -> np.ndarray:
     return out
 
 
-def pair_phase(grid: Grid, a: int, b: int, J: float, dt: float) -> np.ndarray:
+def pair_phase(grid, a: int, b: int, J: float, dt: float) -> np.ndarray:
     """D_ab[s_a, s_b] = exp(-i J dt sum over bonds crossing blocks a, b of z z').
 
     The ZZ layer exp(-i dt H_ZZ) is diagonal; restricted to the bonds between
@@ -147,7 +234,7 @@ def pair_phase(grid: Grid, a: int, b: int, J: float, dt: float) -> np.ndarray:
     return np.exp(-1j * J * dt * energy)
 
 
-def pair_coupled(grid: Grid, a: int, b: int) -> bool:
+def pair_coupled(grid, a: int, b: int) -> bool:
     qa, qb = set(grid.block_qubits(a)), set(grid.block_qubits(b))
     for (q1, q2) in grid.zz_bonds():
         if (q1 in qa and q2 in qb) or (q1 in qb and q2 in qa):
@@ -155,7 +242,7 @@ def pair_coupled(grid: Grid, a: int, b: int) -> bool:
     return False
 
 
-def intra_phase(grid: Grid, a: int, J: float, dt: float) -> np.ndarray:
+def intra_phase(grid, a: int, J: float, dt: float) -> np.ndarray:
     """D_a[s] = exp(-i J dt sum over bonds inside block a of z z')."""
     qa = grid.block_qubits(a)
     za = block_z_values(grid, a)

@@ -39,7 +39,7 @@ class BlockMPS:
         self.pos = grid.snake()
         self.sites = []
         for b in self.pos:
-            w = len(grid.block_columns(b))
+            w = grid.block_width(b)
             self.sites.append(product_site(w, theta0).reshape(1, 2 ** w, 1))
         self.centre = 0
         self.log_fidelity = 0.0
@@ -65,7 +65,7 @@ class BlockMPS:
         return self._pair_cache[key]
 
     def _single_site_gate(self, block: int, variant: int) -> np.ndarray:
-        w = len(self.grid.block_columns(block))
+        w = self.grid.block_width(block)
         dintra = np.diag(intra_phase(self.grid, block, self.J, self.dt))
         if variant == 0:
             return block_x_layer(w, self.h * self.dt) @ dintra
@@ -145,7 +145,7 @@ class BlockMPS:
     # ---- measurement -------------------------------------------------------
     def block_zsum(self, block: int) -> np.ndarray:
         """z_p(s) = sum over the block's qubits of (1 - 2 bit)."""
-        w = len(self.grid.block_columns(block))
+        w = self.grid.block_width(block)
         s = np.arange(2 ** w)
         bits = np.array([(s >> (w - 1 - j)) & 1 for j in range(w)])
         return (1 - 2 * bits).sum(axis=0).astype(np.float64)

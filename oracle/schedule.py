@@ -23,6 +23,14 @@ chain rows R-2 and 0) carry the phase gate. For odd R one pure SWAP first
 reverses the moving row so that chain rows keep facing same-side blocks.
 The chain order of the rows rotates by one row per step.
 
+Schedule 3 (route and return) works for any lattice, and is the schedule of
+the cubic lattice with one qubit per site (supplement, three-dimensional
+generalisation): the coupled block pairs are taken in the order of their
+chain positions at the start of the step; for a pair at sites pa < pb the
+block at pb is swapped leftwards to pa+1, the phase gate is applied on
+(pa, pa+1), and the block is swapped back, so every pair starts from the same
+chain order and the order is unchanged after the step.
+
 Ops are tuples:
   ("U2", site, swap, gate, block_at_site, block_at_site_plus_1)
   ("U1", site, variant, block)   variant 0: U_X(h dt) * D_intra   (order 1)
@@ -34,9 +42,49 @@ from __future__ import annotations
 from .lattice import Grid, pair_coupled
 
 
-def step_ops(grid: Grid, pos: list[int], order: int = 1, schedule: int = 1) -> list[tuple]:
+def coupled_pairs(grid) -> list[tuple[int, int]]:
+    """Unordered block pairs joined by at least one ZZ bond."""
+    blk = grid.block_of_qubit()
+    out = set()
+    for (q1, q2) in grid.zz_bonds():
+        a, b = blk[q1], blk[q2]
+        if a != b:
+            out.add((min(a, b), max(a, b)))
+    return sorted(out)
+
+
+def route_return_ops(grid, pos: list[int], order: int) -> list[tuple]:
+    ops: list[tuple] = []
+
+    def u2(site: int, swap: bool, gate: bool):
+        a, b = pos[site], pos[site + 1]
+        ops.append(("U2", site, int(swap), int(gate), a, b))
+        if swap:
+            pos[site], pos[site + 1] = pos[site + 1], pos[site]
+
+    if order == 2:
+        for p in range(len(pos)):
+            ops.append(("U1", p, 1, pos[p]))
+    where = {b: i for i, b in enumerate(pos)}
+    pairs = sorted(coupled_pairs(grid),
+                   key=lambda ab: (min(where[ab[0]], where[ab[1]]), max(where[ab[0]], where[ab[1]])))
+    for (a, b) in pairs:
+        pa, pb = sorted((where[a], where[b]))
+        for p in range(pb - 1, pa, -1):
+            u2(p, True, False)
+        u2(pa, False, True)
+        for p in range(pa + 1, pb):
+            u2(p, True, False)
+    for p in range(len(pos)):
+        ops.append(("U1", p, 0 if order == 1 else 2, pos[p]))
+    return ops
+
+
+def step_ops(grid, pos: list[int], order: int = 1, schedule: int = 1) -> list[tuple]:
     """Ops of one Trotter step starting from chain order ``pos``; ``pos`` is
     updated in place to the order at the end of the step."""
+    if schedule == 3:
+        return route_return_ops(grid, pos, order)
     R = grid.rows
     rotating = schedule == 2 and grid.periodic and R >= 3
     ops: list[tuple] = []
@@ -80,7 +128,7 @@ def step_ops(grid: Grid, pos: list[int], order: int = 1, schedule: int = 1) -> l
     return ops
 
 
-def schedule(grid: Grid, nsteps: int, order: int = 1, schedule_id: int = 1) -> list[tuple]:
+def schedule(grid, nsteps: int, order: int = 1, schedule_id: int = 1) -> list[tuple]:
     pos = grid.snake()
     out = []
     for _ in range(nsteps):

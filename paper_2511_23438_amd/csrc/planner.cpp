@@ -16,14 +16,22 @@ namespace mpsim {
 
 mps_status validate(const mps_config* cfg, const char** msg) {
   if (!cfg) { *msg = "config is NULL"; return MPS_E_INVAL; }
-  if (cfg->rows < 1 || cfg->cols < 2) { *msg = "need rows >= 1 and cols >= 2"; return MPS_E_INVAL; }
-  if (cfg->cols > 8) { *msg = "cols > 8 (block width > 4, d > 16) unsupported"; return MPS_E_UNSUPPORTED; }
-  if (cfg->rows > 64) { *msg = "rows > 64 unsupported"; return MPS_E_UNSUPPORTED; }
+  if (cfg->reserved != 0) { *msg = "reserved must be 0"; return MPS_E_INVAL; }
+  if (cfg->layers < 0) { *msg = "layers must be >= 0"; return MPS_E_INVAL; }
+  if (cfg->layers >= 2) {
+    if (cfg->rows < 1 || cfg->cols < 1) { *msg = "cube extents must be >= 1"; return MPS_E_INVAL; }
+    if ((long)cfg->rows * cfg->cols * cfg->layers > 256) { *msg = "cube with > 256 sites unsupported"; return MPS_E_UNSUPPORTED; }
+    if (cfg->schedule != 3) { *msg = "the cube needs schedule 3"; return MPS_E_INVAL; }
+  } else {
+    if (cfg->rows < 1 || cfg->cols < 2) { *msg = "need rows >= 1 and cols >= 2"; return MPS_E_INVAL; }
+    if (cfg->cols > 8) { *msg = "cols > 8 (block width > 4, d > 16) unsupported"; return MPS_E_UNSUPPORTED; }
+    if (cfg->rows > 64) { *msg = "rows > 64 unsupported"; return MPS_E_UNSUPPORTED; }
+  }
   if (cfg->chi_max < 1) { *msg = "chi_max must be >= 1"; return MPS_E_INVAL; }
   if (cfg->chi_max > 4096) { *msg = "chi_max > 4096 unsupported"; return MPS_E_UNSUPPORTED; }
   if (cfg->precision < 0 || cfg->precision > 2) { *msg = "bad precision"; return MPS_E_INVAL; }
   if (cfg->trotter_order != 1 && cfg->trotter_order != 2) { *msg = "trotter_order must be 1 or 2"; return MPS_E_INVAL; }
-  if (cfg->schedule != 1 && cfg->schedule != 2) { *msg = "schedule must be 1 or 2"; return MPS_E_INVAL; }
+  if (cfg->schedule < 1 || cfg->schedule > 3) { *msg = "schedule must be 1, 2 or 3"; return MPS_E_INVAL; }
   if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
   if (cfg->eig_path < 0 || cfg->eig_path > 2) { *msg = "eig_path must be 0, 1 or 2"; return MPS_E_INVAL; }
   if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
@@ -32,14 +40,7 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   return MPS_OK;
 }
 
-std::vector<int> Plan::snake() const {
-  std::vector<int> pos;
-  for (int r = 0; r < R; ++r) {
-    if (r % 2 == 0) { pos.push_back(2 * r); pos.push_back(2 * r + 1); }
-    else { pos.push_back(2 * r + 1); pos.push_back(2 * r); }
-  }
-  return pos;
-}
+std::vector<int> Plan::snake() const { return snake_order; }
 
 void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
   auto u2 = [&](int site, int swap, int gate) {
@@ -55,6 +56,29 @@ void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
     o.kind = 2; o.site = site; o.variant = variant; o.block_a = pos[site]; o.block_b = -1;
     out.push_back(o);
   };
+  if (schedule == 3) {
+    // route and return: coupled pairs in the order of their chain positions
+    // at the start of the step; the block at pb travels to pa+1 by SWAP
+    // updates, the phase gate acts on (pa, pa+1), and the block travels back
+    if (order == 2)
+      for (int p = 0; p < N; ++p) u1(p, 1);
+    std::vector<int> where(nb, 0);
+    for (int p = 0; p < N; ++p) where[pos[p]] = p;
+    std::vector<std::pair<int, int>> pairs;  // (pa, pb)
+    for (int a = 0; a < nb; ++a)
+      for (int b = a + 1; b < nb; ++b)
+        if (coupled(a, b) >= 0)
+          pairs.push_back({std::min(where[a], where[b]), std::max(where[a], where[b])});
+    std::sort(pairs.begin(), pairs.end());
+    for (auto& pr : pairs) {
+      const int pa = pr.first, pb = pr.second;
+      for (int p = pb - 1; p > pa; --p) u2(p, 1, 0);
+      u2(pa, 0, 1);
+      for (int p = pa + 1; p < pb; ++p) u2(p, 1, 0);
+    }
+    for (int p = 0; p < N; ++p) u1(p, order == 1 ? 0 : 2);
+    return;
+  }
   const bool rotating = schedule == 2 && periodic && R >= 3;
   const int nfacing = rotating ? R - 2 : R - 1;
   if (order == 2)
@@ -89,15 +113,54 @@ void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
 
 static int zval(int s, int w, int j) { return 1 - 2 * ((s >> (w - 1 - j)) & 1); }
 
-void build_plan(const mps_config* cfg, Plan& p) {
-  p.R = cfg->rows; p.C = cfg->cols; p.n = p.R * p.C; p.N = 2 * p.R;
-  p.chi = cfg->chi_max; p.order = cfg->trotter_order; p.periodic = cfg->periodic;
-  p.schedule = cfg->schedule;
-  p.eig_path = cfg->eig_path;
-  p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
+// Cube: qubit (x, y, z) -> (x*Ly + y)*Lz + z, one qubit per block; snake
+// with x slowest, rows y alternating direction per layer, z alternating per
+// row visited; neighbours along each axis (wrap only when periodic).
+static void cube_geometry(const mps_config* cfg, Plan& p) {
+  const int lx = cfg->rows, ly = cfg->cols, lz = cfg->layers;
+  p.R = lx; p.C = ly; p.Lz = lz;
+  p.n = lx * ly * lz; p.N = p.n; p.nb = p.n;
+  p.wL = p.wR = 1;
+  p.dmax = 2;
+  p.block_width.assign(p.nb, 1);
+  p.block_qubits.assign(p.nb, {});
+  for (int q = 0; q < p.n; ++q) p.block_qubits[q].push_back(q);
+  auto idx = [&](int x, int y, int z) { return (x * ly + y) * lz + z; };
+  p.snake_order.clear();
+  int t = 0;
+  for (int x = 0; x < lx; ++x)
+    for (int yy = 0; yy < ly; ++yy, ++t) {
+      const int y = (x % 2 == 0) ? yy : ly - 1 - yy;
+      for (int zz = 0; zz < lz; ++zz) p.snake_order.push_back(idx(x, y, (t % 2 == 0) ? zz : lz - 1 - zz));
+    }
+  std::set<std::pair<int, int>> seen;
+  p.bonds.clear();
+  const int dims[3] = {lx, ly, lz};
+  for (int x = 0; x < lx; ++x)
+    for (int y = 0; y < ly; ++y)
+      for (int z = 0; z < lz; ++z)
+        for (int ax = 0; ax < 3; ++ax) {
+          int c[3] = {x, y, z};
+          c[ax] += 1;
+          if (c[ax] >= dims[ax]) {
+            if (!p.periodic || dims[ax] < 2) continue;
+            c[ax] = 0;
+          }
+          const int q = idx(x, y, z), q2 = idx(c[0], c[1], c[2]);
+          if (q == q2) continue;
+          std::pair<int, int> key(std::min(q, q2), std::max(q, q2));
+          if (seen.insert(key).second) p.bonds.push_back(key);
+        }
+}
+
+// Grid: half-row blocks (ceil(C/2) and floor(C/2) columns), row snake of
+// blocks, right and down neighbours with wrap.
+static void grid_geometry(const mps_config* cfg, Plan& p) {
+  p.R = cfg->rows; p.C = cfg->cols; p.Lz = 0;
+  p.n = p.R * p.C; p.N = 2 * p.R; p.nb = 2 * p.R;
   p.wL = (p.C + 1) / 2; p.wR = p.C / 2;
   p.dmax = 1 << p.wL;
-  int nb = p.nblocks();
+  const int nb = p.nb;
   p.block_width.assign(nb, 0);
   p.block_qubits.assign(nb, {});
   for (int r = 0; r < p.R; ++r) {
@@ -105,6 +168,11 @@ void build_plan(const mps_config* cfg, Plan& p) {
     p.block_width[2 * r + 1] = p.wR;
     for (int c = 0; c < p.wL; ++c) p.block_qubits[2 * r].push_back(r * p.C + c);
     for (int c = p.wL; c < p.C; ++c) p.block_qubits[2 * r + 1].push_back(r * p.C + c);
+  }
+  p.snake_order.clear();
+  for (int r = 0; r < p.R; ++r) {
+    if (r % 2 == 0) { p.snake_order.push_back(2 * r); p.snake_order.push_back(2 * r + 1); }
+    else { p.snake_order.push_back(2 * r + 1); p.snake_order.push_back(2 * r); }
   }
   // ZZ bonds: right and down neighbours with wrap, unordered pairs kept once
   std::set<std::pair<int, int>> seen;
@@ -124,6 +192,16 @@ void build_plan(const mps_config* cfg, Plan& p) {
         if (seen.insert(key).second) p.bonds.push_back(key);
       }
     }
+}
+
+void build_plan(const mps_config* cfg, Plan& p) {
+  p.chi = cfg->chi_max; p.order = cfg->trotter_order; p.periodic = cfg->periodic;
+  p.schedule = cfg->schedule;
+  p.eig_path = cfg->eig_path;
+  p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
+  if (cfg->layers >= 2) cube_geometry(cfg, p);
+  else grid_geometry(cfg, p);
+  const int nb = p.nb;
   std::vector<int> blk_of(p.n), idx_in(p.n);
   for (int b = 0; b < nb; ++b)
     for (size_t j = 0; j < p.block_qubits[b].size(); ++j) {

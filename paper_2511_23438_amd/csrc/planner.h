@@ -1,5 +1,6 @@
-// Host-side planning of a block-MPS instance: grid geometry, half-row blocks,
-// snake order, the block-pair update schedule, gate tables and buffer sizes.
+// Host-side planning of a block-MPS instance: lattice geometry (a grid with
+// half-row blocks, or a cube with one qubit per site), snake order, the
+// two-site update schedule, gate tables and buffer sizes.
 #pragma once
 #include <complex>
 #include <cstdint>
@@ -22,6 +23,9 @@ struct Op {          // one entry of the step schedule
 
 struct Plan {
   int R = 0, C = 0, n = 0, N = 0;  // grid, qubits, sites
+  int Lz = 0;                      // cube depth (0: two-dimensional grid)
+  int nb = 0;                      // blocks
+  std::vector<int> snake_order;    // block held by each site at the start
   int chi = 0, order = 1, periodic = 1, schedule = 1, eig_path = 0;
   double J = 0, h = 0, dt = 0, theta0 = 0;
   int wL = 0, wR = 0, dmax = 1;
@@ -36,7 +40,7 @@ struct Plan {
   std::vector<std::vector<zc>> site_gate[3];  // [variant][block] d x d
   std::vector<std::vector<double>> zsum;      // [block] d entries
 
-  int nblocks() const { return 2 * R; }
+  int nblocks() const { return nb; }
   int dim(int block) const { return 1 << block_width[block]; }
   int coupled(int a, int b) const {
     if (a == b) return -1;

@@ -43,7 +43,8 @@ class MpsConfig(C.Structure):
                 ("precision", C.c_int32), ("trotter_order", C.c_int32),
                 ("schedule", C.c_int32), ("periodic", C.c_int32), ("eig_path", C.c_int32),
                 ("J", C.c_double), ("h", C.c_double), ("dt", C.c_double),
-                ("theta0", C.c_double), ("seed", C.c_uint64)]
+                ("theta0", C.c_double), ("seed", C.c_uint64), ("layers", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class MpsObs(C.Structure):
@@ -120,9 +121,11 @@ def _check(st: int, handle=None) -> None:
 def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
                 dt: float = 0.25, theta0: float = math.pi / 18, order: int = 1,
                 precision: str = "fp64", periodic: bool = True, seed: int = 0,
-                schedule: int = 1, eig_path: int = 0) -> MpsConfig:
+                schedule: int = 1, eig_path: int = 0, layers: int = 0) -> MpsConfig:
+    """rows x cols grid with half-row blocks, or with layers >= 2 the
+    rows x cols x layers cube with one qubit per site (schedule 3)."""
     return MpsConfig(rows, cols, chi, PRECISION[precision], order, schedule,
-                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed)
+                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0)
 
 
 def config_from_instance(inst, seed: int = 0) -> MpsConfig:

@@ -110,17 +110,20 @@ def snake_dims(rows: int, cols: int) -> list[int]:
 
 
 def random_mps(rows: int, cols: int, chi: int, seed: int,
-               centre: int | None = None) -> tuple[list[np.ndarray], int]:
+               centre: int | None = None, dims: list[int] | None = None
+               ) -> tuple[list[np.ndarray], int]:
     """Seeded random normalised MPS in mixed canonical form: sites left of
     `centre` left-orthonormal, sites right of it right-orthonormal, the norm
     on site `centre` (default: the last site); bonds at min(chi, products of
-    local dims).
+    local dims). `dims` overrides the local dimensions of the grid's snake
+    (e.g. [2] * n for a lattice with one qubit per site).
 
     A symmetry-free input state: the lattice symmetries of a uniform product
     state give exactly degenerate Schmidt values, which make truncations
     non-unique; a random state has none."""
     g = rng(seed)
-    dims = snake_dims(rows, cols)
+    if dims is None:
+        dims = snake_dims(rows, cols)
     N = len(dims)
     c = N - 1 if centre is None else int(centre)
     bonds = [1]

@@ -301,3 +301,69 @@ def test_one_and_two_stage_agree_on_wide_gram():
     print("f", f1, f2)
     assert np.max(np.abs(f1 - f2)) < TOL
     assert abs(o1["z"] - o2["z"]) < TOL and abs(o1["z2"] - o2["z2"]) < TOL
+
+
+@pytest.mark.parametrize("shape,chi,steps,order", [((2, 2, 3), 64, 2, 1), ((2, 2, 2), 16, 3, 2),
+                                                    ((1, 3, 4), 64, 2, 1)])
+def test_cube_full_bond_dimension_matches_state_vector(shape, chi, steps, order):
+    """Cube with one qubit per site (open boundaries), route-and-return
+    schedule: at full bond dimension the HIP path is the exact Trotter state."""
+    from oracle.lattice import Cube
+    lx, ly, lz = shape
+    g = Cube(lx, ly, lz)
+    th = 0.6
+    sim = mpsim.Simulation(mpsim.make_config(lx, ly, chi, theta0=th, order=order, schedule=3,
+                                             layers=lz, periodic=False))
+    sv = osv.StateVector(g, th, J, H, DT, order)
+    for _ in range(steps):
+        sim.step(1)
+        sv.step()
+        a, b = sim.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"]) < 1e-12
+    psi = sim.to_statevector()
+    assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < TOL
+
+
+@pytest.mark.parametrize("shape,chi,steps,seed", [((2, 2, 3), 8, 2, 51), ((3, 3, 3), 16, 1, 52),
+                                                   ((2, 3, 4), 12, 1, 54)])
+def test_cube_truncating_parity(shape, chi, steps, seed):
+    """Cube, symmetry-free seeded start state, truncating bond dimension: all
+    observables, log F and every per-update f agree with the oracle."""
+    from oracle.lattice import Cube
+    lx, ly, lz = shape
+    g = Cube(lx, ly, lz)
+    sites, centre = workloads.random_mps(lx, ly, chi, seed, dims=[2] * g.n)
+    sim = mpsim.Simulation(mpsim.make_config(lx, ly, chi, theta0=0.0, schedule=3, layers=lz,
+                                             periodic=False))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(g, chi, sites, centre, J, H, DT, schedule=3)
+    for _ in range(steps):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert len(f_gpu) == len(f_ora)
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL
+    assert sim.bond_dims() == ora.bond_dims()
+
+
+@pytest.mark.parametrize("R,C,chi,seed", [(4, 4, 16, 61), (3, 5, 24, 62)])
+def test_route_return_schedule_truncating_parity(R, C, chi, seed):
+    """Route-and-return schedule on the grid with half-row blocks."""
+    sites, centre = workloads.random_mps(R, C, chi, seed)
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, schedule=3))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(Grid(R, C), chi, sites, centre, J, H, DT, schedule=3)
+    sim.step(1)
+    ora.step()
+    a, b = sim.measure(), ora.measure()
+    assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL

@@ -313,3 +313,104 @@ def test_planted_missing_swap_is_caught(monkeypatch):
         return f
     monkeypatch.setattr(mps.BlockMPS, "apply_u2", bad)
     assert _t4_error() > 1e-6
+
+
+# --------------------------------------------------------------------------
+# cubic lattice, one qubit per site (open boundaries), route-and-return schedule
+def _dense_h_cube(lx, ly, lz):
+    """Independent Kronecker construction on the cube: neighbours differ by
+    one in exactly one coordinate (no wrap)."""
+    n = lx * ly * lz
+    I2 = np.eye(2)
+    Zm = np.diag([1.0, -1.0])
+    Xm = np.array([[0.0, 1.0], [1.0, 0.0]])
+
+    def op(single, q):
+        out = np.ones((1, 1))
+        for k in range(n):
+            out = np.kron(out, single if k == q else I2)
+        return out
+
+    coords = [(x, y, z) for x in range(lx) for y in range(ly) for z in range(lz)]
+    idx = {c: (c[0] * ly + c[1]) * lz + c[2] for c in coords}
+    pairs = set()
+    for c1 in coords:
+        for c2 in coords:
+            if sum(abs(u - v) for u, v in zip(c1, c2)) == 1:
+                a, b = idx[c1], idx[c2]
+                pairs.add((min(a, b), max(a, b)))
+    hzz = sum(op(Zm, a) @ op(Zm, b) for (a, b) in pairs)
+    hx = sum(op(Xm, q) for q in range(n))
+    return hzz, hx, len(pairs)
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (2, 2, 3), (1, 3, 3)])
+@pytest.mark.parametrize("order", [1, 2])
+def test_cube_statevector_matches_dense_expm(shape, order):
+    from oracle.lattice import Cube
+    hzz, hx, npairs = _dense_h_cube(*shape)
+    g = Cube(*shape)
+    assert len(g.zz_bonds()) == npairs
+    th = 0.41
+    if order == 1:
+        U = scipy.linalg.expm(-1j * DT * H * hx) @ scipy.linalg.expm(-1j * DT * J * hzz)
+    else:
+        half = scipy.linalg.expm(-0.5j * DT * H * hx)
+        U = half @ scipy.linalg.expm(-1j * DT * J * hzz) @ half
+    psi = np.ones(1)
+    for _ in range(g.n):
+        psi = np.kron(psi, [math.cos(th / 2), math.sin(th / 2)])
+    sv = statevector.StateVector(g, th, J, H, DT, order)
+    for _ in range(3):
+        psi = U @ psi
+        sv.step()
+    assert np.max(np.abs(sv.psi - psi)) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (3, 3, 3), (2, 3, 4), (4, 4, 4), (1, 1, 5)])
+def test_cube_bonds_and_snake(shape):
+    from oracle.lattice import Cube
+    lx, ly, lz = shape
+    g = Cube(*shape)
+    bonds = set(g.zz_bonds())
+    assert len(bonds) == (lx - 1) * ly * lz + lx * (ly - 1) * lz + lx * ly * (lz - 1)
+    sn = g.snake()
+    assert sorted(sn) == list(range(g.n))
+    # consecutive sites of the snake are nearest neighbours
+    assert all((min(a, b), max(a, b)) in bonds for a, b in zip(sn, sn[1:]))
+
+
+@pytest.mark.parametrize("lattice", ["cube223", "cube222", "grid44", "grid35"])
+def test_route_return_schedule_gates_each_pair_once(lattice):
+    from oracle.lattice import Cube
+    from oracle.schedule import coupled_pairs
+    g = {"cube223": Cube(2, 2, 3), "cube222": Cube(2, 2, 2), "grid44": Grid(4, 4),
+         "grid35": Grid(3, 5)}[lattice]
+    pos = g.snake()
+    start = list(pos)
+    for _ in range(2):
+        ops = step_ops(g, pos, 1, 3)
+        gated = [frozenset((o[4], o[5])) for o in ops if o[0] == "U2" and o[3]]
+        assert len(gated) == len(set(gated))
+        assert set(gated) == {frozenset(p) for p in coupled_pairs(g)}
+        assert pos == start            # every routed block returns
+        # a gated update always acts on the two blocks of a coupled pair
+        assert all(frozenset((o[4], o[5])) in set(gated) for o in ops if o[0] == "U2" and o[3])
+
+
+@pytest.mark.parametrize("lattice,chi,steps,order", [("cube223", 64, 3, 1), ("cube222", 16, 3, 2),
+                                                     ("grid34", 64, 2, 1)])
+def test_t4_route_return_full_chi_is_exact(lattice, chi, steps, order):
+    """Route-and-return schedule at full bond dimension == exact state vector
+    (cube: one qubit per site, open boundaries)."""
+    from oracle.lattice import Cube
+    g = {"cube223": Cube(2, 2, 3), "cube222": Cube(2, 2, 2), "grid34": Grid(3, 4)}[lattice]
+    m = mps.BlockMPS(g, chi, 0.6, J, H, DT, order, schedule=3)
+    sv = statevector.StateVector(g, 0.6, J, H, DT, order)
+    for _ in range(steps):
+        m.step()
+        sv.step()
+        a, b = m.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < 1e-10 and abs(a["z2"] - b["z2"]) < 1e-10
+    assert abs(m.log_fidelity) < 1e-12
+    assert abs(abs(np.vdot(sv.psi, m.to_statevector())) ** 2 - 1) < 1e-10
