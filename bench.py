@@ -180,6 +180,36 @@ def concurrent(rows: int, cols: int, chi: int, precision: str, schedule: int, co
             "z": [o["z"] for o in obs], "fidelity": [o["fidelity"] for o in obs]}
 
 
+def cube_rate(shape: tuple[int, int, int], chi: int, precision: str, steps: int,
+              seed: int) -> dict:
+    """Trotter steps/s of the cubic lattice with one qubit per site (open
+    boundaries, route-and-return schedule) from a seeded random MPS at
+    saturated bonds; each step includes one measurement."""
+    import torch
+    from paper_2511_23438_amd import mpsim, workloads
+    lx, ly, lz = shape
+    n = lx * ly * lz
+    cfg = mpsim.make_config(lx, ly, chi, precision=precision, schedule=3, layers=lz,
+                            periodic=False)
+    sim = mpsim.Simulation(cfg)
+    sites, centre = workloads.random_mps(lx, ly, chi, seed, dims=[2] * n)
+    sim.set_state(sites, centre)
+    del sites
+    ops = mpsim.schedule_dump(cfg, 1)
+    nu2 = int(sum(1 for r in ops if r[0] == 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(1)
+        obs = sim.measure()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.free()
+    return {"workload": "tfim_cube_%dx%dx%d_chi%d" % (lx, ly, lz, chi), "qubits": n,
+            "two_site_updates_per_step": nu2, "steps": steps, "seconds": el,
+            "steps_per_s": steps / el, "z": obs["z"], "fidelity": obs["fidelity"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +233,10 @@ def main() -> int:
                     help="admission window of the served run (0 disables it)")
     ap.add_argument("--serve-chi-cap", type=int, default=32)
     ap.add_argument("--serve-requests", type=int, default=8)
+    ap.add_argument("--cube", default="",
+                    help="also time the cubic lattice LX,LY,LZ (one qubit per site)")
+    ap.add_argument("--cube-chi", type=int, default=64)
+    ap.add_argument("--cube-steps", type=int, default=2)
     ap.add_argument("--instances", type=int, default=0,
                     help="also time this many concurrent instances of the workload")
     args = ap.parse_args()
@@ -319,6 +353,11 @@ def main() -> int:
         log("served: %s" % {k: out["served"][k] for k in ("completed", "steps_per_s",
                                                          "step_latency_ms_p50",
                                                          "step_latency_ms_p99")})
+    if args.cube:
+        shape = tuple(int(v) for v in args.cube.split(","))
+        log("cube run: %s chi %d" % (shape, args.cube_chi))
+        out["cube"] = cube_rate(shape, args.cube_chi, args.precision, args.cube_steps, args.seed)
+        log("cube: %.3f steps/s" % out["cube"]["steps_per_s"])
     if args.instances > 0:
         log("concurrent run: %d instances" % args.instances)
         out["concurrent"] = concurrent(args.rows, args.cols, args.chi, args.precision,

@@ -204,8 +204,12 @@ class Simulation:
         self.h = H()
         _check(_lib.mps_init_product(C.byref(cfg), ap, C.c_void_p(self.stream),
                                      C.byref(self.h)))
-        self.n = cfg.rows * cfg.cols
-        self.N = 2 * cfg.rows
+        if cfg.layers >= 2:      # cube: one qubit per site
+            self.n = cfg.rows * cfg.cols * cfg.layers
+            self.N = self.n
+        else:                    # grid: two half-row blocks per row
+            self.n = cfg.rows * cfg.cols
+            self.N = 2 * cfg.rows
 
     # -- core -------------------------------------------------------------
     def step(self, nsteps: int = 1) -> None:
