@@ -127,6 +127,85 @@ class BlockMPS:
                                     f=f, sv=S.copy(), q=q, gap=gap))
         return f
 
+    def bond_cap(self, bond: int) -> int:
+        """Largest rank bond ``bond`` (between sites bond-1 and bond) can
+        carry: the smaller of the Hilbert-space dimensions on its two sides."""
+        dims = [A.shape[1] for A in self.sites]
+        left = math.prod(dims[:bond])
+        right = math.prod(dims[bond:])
+        return min(left, right)
+
+    def apply_zz_mpo(self, sa: int, sb: int, ja: int, jb: int) -> list[float]:
+        """One ZZ gate exp(-i J dt Z Z') between bit ja of the block at site
+        sa and bit jb of the block at site sb > sa, as a rank-2 matrix product
+        operator (results section): exp(-i phi Z Z') = cos(phi) I I
+        - i sin(phi) Z Z', the operator index k in {0, 1} runs along the
+        chain from sa to sb, so every bond between them doubles (new bond
+        index = 2 * old + k). The MPS is then brought back to canonical form
+        (centre on site sa, sites sa+1..sb right-orthonormal by LQ sweeps) and
+        the doubled bonds are truncated one by one from left to right, each by
+        the SVD of the centre site with the centre on that bond, keeping
+        q = min(chi, rank bound) values. Returns the truncation fidelities."""
+        phi = self.J * self.dt
+        self.move_centre(sa)
+        wa = int(round(math.log2(self.sites[sa].shape[1])))
+        wb = int(round(math.log2(self.sites[sb].shape[1])))
+        za = np.array([1 - 2 * ((s >> (wa - 1 - ja)) & 1) for s in range(2 ** wa)], dtype=float)
+        zb = np.array([1 - 2 * ((s >> (wb - 1 - jb)) & 1) for s in range(2 ** wb)], dtype=float)
+        # first site: right bond gains k with weights (cos phi, -i sin phi z)
+        A = self.sites[sa]
+        b0, d, b1 = A.shape
+        X = np.empty((b0, d, b1, 2), dtype=np.complex128)
+        X[..., 0] = math.cos(phi) * A
+        X[..., 1] = -1j * math.sin(phi) * za[None, :, None] * A
+        self.sites[sa] = X.reshape(b0, d, 2 * b1)
+        # sites strictly between: k passes through unchanged
+        for p in range(sa + 1, sb):
+            A = self.sites[p]
+            b0, d, b1 = A.shape
+            X = np.zeros((b0, 2, d, b1, 2), dtype=np.complex128)
+            X[:, 0, :, :, 0] = A
+            X[:, 1, :, :, 1] = A
+            self.sites[p] = X.reshape(2 * b0, d, 2 * b1)
+        # last site: left bond gains k with weights (1, z')
+        A = self.sites[sb]
+        b0, d, b1 = A.shape
+        X = np.empty((b0, 2, d, b1), dtype=np.complex128)
+        X[:, 0] = A
+        X[:, 1] = zb[None, :, None] * A
+        self.sites[sb] = X.reshape(2 * b0, d, b1)
+        # canonical form again: LQ sweeps from sb down to sa+1
+        self.centre = sb
+        self.move_centre(sa)
+        out = []
+        for p in range(sa, sb):
+            out.append(self._truncate_bond(p))
+        return out
+
+    def _truncate_bond(self, p: int) -> float:
+        """Truncate the bond between sites p and p+1 with the centre on site
+        p: SVD of the site as a (b d) x b' matrix, keep the top q singular
+        values, renormalise, and move the centre to p+1."""
+        assert self.centre == p
+        A = self.sites[p]
+        b0, d, b1 = A.shape
+        U, S, Vh = np.linalg.svd(A.reshape(b0 * d, b1), full_matrices=False)
+        q = min(self.chi, self.bond_cap(p + 1), len(S))
+        total = float(np.sum(S ** 2))
+        kept = float(np.sum(S[:q] ** 2))
+        f = kept / total
+        self.log_fidelity += math.log(f)
+        Sk = S[:q] / math.sqrt(kept)
+        self.sites[p] = U[:, :q].reshape(b0, d, q)
+        self.sites[p + 1] = np.einsum('ij,jsk->isk', Sk[:, None] * Vh[:q], self.sites[p + 1])
+        self.centre = p + 1
+        gap = math.inf
+        if q < len(S) and S[0] > 0:
+            gap = float((S[q - 1] - S[q]) / S[0])
+        self.update_log.append(dict(site=p, swap=False, gate=True, norm2=total,
+                                    f=f, sv=S.copy(), q=q, gap=gap))
+        return f
+
     def apply_u1(self, p: int, U: np.ndarray) -> None:
         self.sites[p] = np.einsum('st,atb->asb', U, self.sites[p])
 
@@ -136,6 +215,9 @@ class BlockMPS:
                 _, site, swap, gate, a, b = op
                 assert (self.pos[site], self.pos[site + 1]) == (a, b)
                 self.apply_u2(site, bool(swap), bool(gate))
+            elif op[0] == "ZZ":
+                _, sa, sb, ja, jb = op
+                self.apply_zz_mpo(sa, sb, ja, jb)
             else:
                 _, site, variant, block = op
                 assert self.pos[site] == block

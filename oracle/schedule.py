@@ -31,8 +31,19 @@ block at pb is swapped leftwards to pa+1, the phase gate is applied on
 (pa, pa+1), and the block is swapped back, so every pair starts from the same
 chain order and the order is unchanged after the step.
 
+Schedule 4 (gate by gate) is the paper's own path (results section): every
+ZZ bond between two different blocks is its own gate, applied to the block
+MPS as a rank-2 matrix product operator that doubles the virtual bonds
+between the two blocks, each followed by truncation of those bonds; bonds
+inside a block are applied locally with the single-site layer. Blocks never
+move. The gates are taken in the order of (site of the first block, site of
+the second block, bit of the first qubit, bit of the second qubit).
+
 Ops are tuples:
   ("U2", site, swap, gate, block_at_site, block_at_site_plus_1)
+  ("ZZ", site_a, site_b, bit_a, bit_b)  site_a < site_b; bit j of the fused
+                                        index of the block (j = 0 the most
+                                        significant)
   ("U1", site, variant, block)   variant 0: U_X(h dt) * D_intra   (order 1)
                                  variant 1: D_intra * U_X(h dt/2) (order 2, first)
                                  variant 2: U_X(h dt/2)           (order 2, last)
@@ -80,11 +91,39 @@ def route_return_ops(grid, pos: list[int], order: int) -> list[tuple]:
     return ops
 
 
+def gate_by_gate_ops(grid, pos: list[int], order: int) -> list[tuple]:
+    """Schedule 4: one op per ZZ bond joining two different blocks."""
+    ops: list[tuple] = []
+    if order == 2:
+        for p in range(len(pos)):
+            ops.append(("U1", p, 1, pos[p]))
+    blk = grid.block_of_qubit()
+    where = {b: i for i, b in enumerate(pos)}
+    gates = []
+    for (q1, q2) in grid.zz_bonds():
+        b1, b2 = blk[q1], blk[q2]
+        if b1 == b2:
+            continue
+        s1, s2 = where[b1], where[b2]
+        if s1 > s2:
+            q1, q2, b1, b2, s1, s2 = q2, q1, b2, b1, s2, s1
+        j1 = grid.block_qubits(b1).index(q1)
+        j2 = grid.block_qubits(b2).index(q2)
+        gates.append((s1, s2, j1, j2))
+    for (s1, s2, j1, j2) in sorted(gates):
+        ops.append(("ZZ", s1, s2, j1, j2))
+    for p in range(len(pos)):
+        ops.append(("U1", p, 0 if order == 1 else 2, pos[p]))
+    return ops
+
+
 def step_ops(grid, pos: list[int], order: int = 1, schedule: int = 1) -> list[tuple]:
     """Ops of one Trotter step starting from chain order ``pos``; ``pos`` is
     updated in place to the order at the end of the step."""
     if schedule == 3:
         return route_return_ops(grid, pos, order)
+    if schedule == 4:
+        return gate_by_gate_ops(grid, pos, order)
     R = grid.rows
     rotating = schedule == 2 and grid.periodic and R >= 3
     ops: list[tuple] = []

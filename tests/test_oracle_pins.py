@@ -414,3 +414,92 @@ def test_t4_route_return_full_chi_is_exact(lattice, chi, steps, order):
         assert abs(a["z"] - b["z"]) < 1e-10 and abs(a["z2"] - b["z2"]) < 1e-10
     assert abs(m.log_fidelity) < 1e-12
     assert abs(abs(np.vdot(sv.psi, m.to_statevector())) ** 2 - 1) < 1e-10
+
+
+# ---- gate-by-gate path (schedule 4): each inter-block ZZ as a rank-2 MPO ----
+
+@pytest.mark.parametrize("R,C,chi,steps,order", [(3, 3, 64, 3, 1), (2, 4, 16, 3, 1),
+                                                  (3, 4, 64, 2, 2), (4, 2, 16, 3, 1)])
+def test_gate_by_gate_full_chi_is_exact(R, C, chi, steps, order):
+    """At full bond dimension the MPO route reproduces the exact Trotterised
+    state: a wrong MPO weight, sign or bond ordering breaks the overlap."""
+    g = Grid(R, C)
+    m = mps.BlockMPS(g, chi, 0.6, J, H, DT, order, schedule=4)
+    sv = statevector.StateVector(g, 0.6, J, H, DT, order)
+    for _ in range(steps):
+        m.step()
+        sv.step()
+        a, b = m.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < 1e-10 and abs(a["z2"] - b["z2"]) < 1e-10
+        assert abs(a["log_fidelity"]) < 1e-11
+    assert abs(abs(np.vdot(sv.psi, m.to_statevector())) ** 2 - 1) < 1e-10
+    # every bond is back within its cap
+    dims = [g.block_dim(b) for b in m.pos]
+    for bond, b in enumerate(m.bond_dims()):
+        assert b <= min(int(np.prod(dims[:bond])), int(np.prod(dims[bond:])))
+
+
+@pytest.mark.parametrize("shape,order", [((2, 2, 2), 1), ((1, 3, 3), 2)])
+def test_gate_by_gate_cube_full_chi_is_exact(shape, order):
+    from oracle.lattice import Cube
+    g = Cube(*shape)
+    m = mps.BlockMPS(g, 64, 0.5, J, H, DT, order, schedule=4)
+    sv = statevector.StateVector(g, 0.5, J, H, DT, order)
+    for _ in range(2):
+        m.step()
+        sv.step()
+    assert abs(abs(np.vdot(sv.psi, m.to_statevector())) ** 2 - 1) < 1e-10
+
+
+@pytest.mark.parametrize("R,C,gates,truncations", [(4, 4, 24, 56), (5, 6, 40, 106),
+                                                    (6, 8, 60, 172), (7, 8, 70, 206)])
+def test_gate_by_gate_counts(R, C, gates, truncations):
+    """One gate per ZZ bond between different blocks (2n bonds minus those
+    inside a block); bond truncations per step = sum of chain distances."""
+    g = Grid(R, C)
+    blk = g.block_of_qubit()
+    inter = sum(1 for (a, b) in g.zz_bonds() if blk[a] != blk[b])
+    assert len(g.zz_bonds()) == 2 * g.n
+    ops = step_ops(g, g.snake(), 1, 4)
+    zz = [o for o in ops if o[0] == "ZZ"]
+    assert len(zz) == inter == gates
+    assert sum(o[2] - o[1] for o in zz) == truncations
+    assert all(o[1] < o[2] for o in zz)
+
+
+def test_gate_by_gate_single_truncation_is_orthogonal_projection():
+    """T5 for the MPO route: from an exact MPS, one gate between neighbouring
+    sites truncated to chi gives |<psi_exact|psi_MPS>|^2 = f, the kept weight."""
+    g = Grid(3, 4)
+    m = mps.BlockMPS(g, 64, 0.7, J, H, DT, 1, schedule=4)
+    m.step()                                     # exact (full chi)
+    psi0 = m.to_statevector()
+    ops = [o for o in step_ops(g, list(m.pos), 1, 4) if o[0] == "ZZ" and o[2] == o[1] + 1]
+    _, sa, sb, ja, jb = [o for o in ops if o[1] == 2][0]     # the middle bond (cap 64)
+    qa = g.block_qubits(m.pos[sa])[ja]
+    qb = g.block_qubits(m.pos[sb])[jb]
+    n = g.n
+    x = np.arange(2 ** n)
+    za = 1 - 2 * ((x >> (n - 1 - qa)) & 1)
+    zb = 1 - 2 * ((x >> (n - 1 - qb)) & 1)
+    exact = np.exp(-1j * J * DT * za * zb) * psi0
+    m.chi = 6
+    fs = m.apply_zz_mpo(sa, sb, ja, jb)
+    assert len(fs) == 1 and fs[0] < 1 - 1e-6
+    psi = m.to_statevector()
+    assert abs(np.linalg.norm(psi) - 1) < 1e-12
+    assert abs(abs(np.vdot(exact, psi)) ** 2 - fs[0]) < 1e-12
+
+
+def test_gate_by_gate_zero_coupling_closed_form():
+    """J = 0: the MPO's second term vanishes; T2's closed form holds and F = 1."""
+    g = Grid(3, 3)
+    th = 0.45
+    m = mps.BlockMPS(g, 4, th, 0.0, H, DT, 1, schedule=4)
+    for s in range(1, 4):
+        m.step()
+        o = m.measure()
+        c = math.cos(2 * H * DT * s)
+        assert abs(o["z"] - math.cos(th) * c) < 1e-12
+        assert abs(o["z2"] - (1 / g.n + (1 - 1 / g.n) * math.cos(th) ** 2 * c ** 2)) < 1e-12
+        assert abs(o["fidelity"] - 1) < 1e-12
