@@ -10,7 +10,11 @@ measurement of <Z_tot>, <Z_tot^2> and F_MPS, with the paper's couplings
 (J = -1, h = 2, dt = 0.25). `--schedule 2` (default) is the rotating-row
 schedule (34 two-site updates per step at 6x8), `--schedule 1` the
 block-pair schedule with routed wrap pairs (54); both apply every coupling
-once per step.
+once per step. `--schedule 4` is the paper's own gate-by-gate path: every
+ZZ bond between two blocks is a rank-2 operator that doubles the bonds
+between them, followed by bond-by-bond truncation (60 gates and 172 bond
+truncations per step at 6x8); its finite-chi results differ from the
+block-pair schedules.
 
 The roofline line times one launch class on the library's stream (HIP
 events, `mps_profile`): `gram` (default) is the float64 Gram-matrix GEMM,
@@ -77,11 +81,50 @@ def read_traffic(kind: str, workload: str):
         return None
 
 
+def cpu_baseline_gate_by_gate(rows: int, cols: int, chi: int, budget_s: float) -> dict:
+    """Oracle timed on one gate of the gate-by-gate path at a reduced bond
+    dimension (a rank-2 operator between neighbouring bulk sites: one LQ
+    step and one bond SVD), extrapolated to chi by the cubic cost and
+    multiplied by the bond truncations of one step."""
+    from oracle import mps as omps
+    from oracle.lattice import Grid
+    from oracle.schedule import step_ops
+    from paper_2511_23438_amd import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    g = Grid(rows, cols)
+    ops = [o for o in step_ops(g, g.snake(), 1, 4) if o[0] == "ZZ"]
+    ntrunc = sum(o[2] - o[1] for o in ops)
+    gate = [o for o in ops if o[2] == o[1] + 1 and o[1] == rows - 1][0]
+    chi_s = 64
+    while True:
+        sites, centre = workloads.random_mps(rows, cols, chi_s, 99, centre=gate[1])
+        m = omps.BlockMPS.from_sites(g, chi_s, sites, centre, -1.0, 2.0, 0.25, schedule=4)
+        t0 = time.perf_counter()
+        m.apply_zz_mpo(*gate[1:])
+        t_s = time.perf_counter() - t0
+        log("cpu baseline sample: chi_s=%d one gate %.2fs" % (chi_s, t_s))
+        if t_s * 8 > budget_s or chi_s * 2 > chi:
+            break
+        chi_s *= 2
+    step_s = t_s * (chi / chi_s) ** 3 * ntrunc
+    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": ("one gate between neighbouring bulk sites (LQ step + bond SVD) of the "
+                       "%dx%d grid at chi=%d took %.2fs; scaled by (chi/%d)^3 over the %d bond "
+                       "truncations of a saturated chi=%d step" % (rows, cols, chi_s, t_s, chi_s,
+                                                                  ntrunc, chi))}
+
+
 def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float, schedule: int = 1) -> dict:
     """Oracle (numpy, float64) timed on a bounded sample of the workload: one
     bulk two-site update of the same grid at a reduced bond dimension,
     extrapolated to chi by the cubic cost of its SVD and summed over the
     updates of one steady-state step."""
+    if schedule == 4:
+        return cpu_baseline_gate_by_gate(rows, cols, chi, budget_s)
     import numpy as np
     from oracle import mps as omps
     from oracle.lattice import Grid
@@ -224,8 +267,9 @@ def main() -> int:
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "c64", "bf16x3"])
     ap.add_argument("--theta0", type=float, default=math.pi / 18)
-    ap.add_argument("--schedule", type=int, default=2, choices=[1, 2],
-                    help="1: wrap pairs routed by SWAPs and back; 2: rotating rows")
+    ap.add_argument("--schedule", type=int, default=2, choices=[1, 2, 4],
+                    help="1: wrap pairs routed by SWAPs and back; 2: rotating rows; "
+                         "4: gate by gate (rank-2 operators, bond truncations)")
     ap.add_argument("--prof", default="gram", choices=sorted(DOMINANT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -295,7 +339,12 @@ def main() -> int:
     # carry less than a tenth of that); other launch classes: every launch
     dblk = 2 ** ((args.cols + 1) // 2)
     nwide = min(args.chi * dblk, dblk ** args.rows)
-    sim.profile(args.prof, min_work=(2.0 * float(nwide) ** 3 if args.prof == "gram" else 0.0))
+    if args.schedule == 4:
+        # bond truncations: Gram of the (chi d) x (2 chi) site on its 2 chi side
+        gram_max = 4.0 * float(min(2 * args.chi, nwide)) ** 2 * float(nwide)
+    else:
+        gram_max = 4.0 * float(nwide) ** 3
+    sim.profile(args.prof, min_work=(0.5 * gram_max if args.prof == "gram" else 0.0))
     torch.cuda.synchronize()
     t_start[0] = time.perf_counter()
     t0 = time.perf_counter()
@@ -337,7 +386,8 @@ def main() -> int:
                    "d": 2 ** ((args.cols + 1) // 2), "sites": 2 * args.rows, "chi": args.chi,
                    "precision": args.precision, "theta0": args.theta0, "J": -1.0, "h": 2.0,
                    "dt": 0.25, "trotter_order": 1,
-                   "schedule": {1: "block-pair", 2: "rotating-rows"}[args.schedule],
+                   "schedule": {1: "block-pair", 2: "rotating-rows",
+                                4: "gate-by-gate"}[args.schedule],
                    "start": ("seeded random MPS at saturated bonds (seed %d)" % args.seed
                              if args.start == "random" else "product state")
                             + (" + %d warmup steps" % args.warmup if args.warmup else "")},

@@ -82,7 +82,13 @@ typedef struct {
                               2: rotating rows (7R-8 / 7R-7 updates/step, even / odd R);
                               3: route and return, any lattice: each coupled block pair in
                                  chain order, the far block swapped next to its partner,
-                                 gated, swapped back */
+                                 gated, swapped back;
+                              4: gate by gate (the results section's own path): every ZZ
+                                 bond between two blocks is a rank-2 matrix product
+                                 operator that doubles the bonds between the blocks, then
+                                 the doubled bonds are truncated one by one with the
+                                 orthogonality centre on the bond; blocks never move.
+                                 Site buffers are sized for the doubled bonds */
   int32_t periodic;        /* 1: periodic in both directions (the paper's TFIM); 0: open */
   int32_t eig_path;        /* truncation eigensolver: 0 automatic (two-stage from a Gram
                               side of MPS_EIG2_MIN on), 1 one-stage Householder
@@ -92,7 +98,7 @@ typedef struct {
   uint64_t seed;           /* seeds the start vectors of the eigensolver (deterministic) */
   int32_t layers;          /* 0 or 1: the rows x cols grid above, half-row blocks. >= 2: the
                               rows x cols x layers cubic lattice with one qubit per site
-                              (d = 2, snake through the cube; schedule must be 3) */
+                              (d = 2, snake through the cube; schedule must be 3 or 4) */
   int32_t reserved;        /* must be 0 */
 } mps_config;
 
@@ -149,7 +155,10 @@ mps_status mps_footprint_bytes(const mps_config* cfg, size_t* bytes);
  * int32: {kind, site, a, b, c, d}. kind 1 = two-site update:
  * {1, site, swap, gate, block at site, block at site+1}; kind 2 = single-site
  * gate: {2, site, variant, block, 0, 0} with variant 0 = U_X(h dt) D_intra,
- * 1 = D_intra U_X(h dt/2), 2 = U_X(h dt/2). *len receives the number of
+ * 1 = D_intra U_X(h dt/2), 2 = U_X(h dt/2); kind 3 = ZZ gate as a rank-2
+ * operator (schedule 4): {3, site_a, site_b, bit_a, bit_b, 0} with site_a <
+ * site_b and bit j of each block's fused index (j = 0 the most significant).
+ * *len receives the number of
  * int32 written (or needed, if cap is too small: then MPS_E_INVAL). Host only. */
 mps_status mps_schedule_dump(const mps_config* cfg, int32_t nsteps, int32_t* ops,
                              int32_t cap, int32_t* len);
@@ -181,7 +190,9 @@ mps_status mps_set_state(mps_handle h, const int32_t* bonds, const double* const
                          int32_t centre);
 
 /* Apply one two-site update on sites (site, site+1): optional SWAP and
- * optional block-pair phase gate, then the truncation (diagnostic / test). */
+ * optional block-pair phase gate, then the truncation (diagnostic / test).
+ * MPS_E_UNSUPPORTED on a schedule-4 handle (its buffers are sized for bond
+ * truncations, not two-site contractions). */
 mps_status mps_apply_two_site(mps_handle h, int32_t site, int32_t swap, int32_t gate);
 
 /* Per-update truncation fidelities f and relative gaps since init (or

@@ -4,9 +4,10 @@
 //      Householder QR of the block below the band and the two-sided update
 //      of the trailing matrix, A22 <- Q^H A22 Q = A22 - V W^H - W V^H with
 //      W = A22 V T - 1/2 V T^H V^H A22 V T. The products run on MFMA GEMMs
-//      (A22 V reads the stored lower triangle as a Hermitian operand), so the
-//      trailing matrix is read a few times per panel instead of once per
-//      column as in the one-stage reduction.
+//      (A22 V reads the stored lower triangle as a Hermitian operand), and
+//      the rank-2k updates of a group of panels are applied together, so
+//      the trailing matrix is read about 1.5 times per panel instead of once
+//      per column as in the one-stage reduction.
 //   2. Band -> real tridiagonal by bulge chasing, eigenvalues only. Sweep j
 //      removes column j below the subdiagonal and chases the bulge down in
 //      steps of HB rows. Each step touches a window of at most 2HB x 2HB
@@ -53,43 +54,97 @@ __global__ void k_band_extract(int n, const cplx* A, long lda, cplx* Ab) {
   }
 }
 
+// Panels are taken in groups of HB_GROUP. Within a group the trailing matrix
+// is not rewritten: the group's reflectors V and their W accumulate, each
+// panel's columns get the earlier updates of the group before its QR, and the
+// product A22 V is formed from the stored matrix and corrected,
+//   A22 V = A22_stored V - Vg (Wg^H V) - Wg (Vg^H V).
+// One rank-2*HB*HB_GROUP update per group then brings the trailing matrix up
+// to date, so it is read and written once per group instead of once per panel.
 void he2hb_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
   const cplx one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
-  for (int p = 0, i0 = 0; i0 + HB < n - 1; ++p, i0 += HB) {
-    const int o = i0 + HB;
-    const int m = n - o;
-    const int kb = std::min(HB, m);
-    cplx* T = w.T1 + (long)p * 4096;
-    cplx* A22 = A + (long)o * lda + o;
-    // panel QR; leaves the explicit V (m x kb, column-major ld vmax) in w.V
-    LinalgWork wp = w;
-    wp.T = T;
-    qr_factor(m, HB, A + (long)i0 * lda + o, 1, lda, wp, s);
-    // X = A22 V (row-major, ld 64)
-    ZGemm gx = zgemm_args(m, kb, m, zop(A22, lda, 1), zop(w.V, w.vmax, 1), w.X2, 64, 0, one, zero);
-    gx.herm_a = 1;
-    zgemm(gx, w.gpart, w.gpart_elems, s, w.prof);
-    // Y = X T (column-major, ld nmax, in w.W)
-    ZGemm gy = zgemm_args(m, kb, kb, zop(w.X2, 64, 0), zop(T, 64, 0), w.W, w.nmax, 1, one, zero);
-    zgemm(gy, nullptr, 0, s, w.prof);
-    // S = V^H Y, Z = T^H S
-    ZGemm gs = zgemm_args(kb, kb, m, zop(w.V, w.vmax, 0, 1), zop(w.W, w.nmax, 1), w.S, 64, 0, one,
-                          zero);
-    zgemm(gs, w.gpart, w.gpart_elems, s, w.prof);
-    ZGemm gz = zgemm_args(kb, kb, kb, zop(T, 64, 1, 1), zop(w.S, 64, 0), w.S2, 64, 0, one, zero);
-    zgemm(gz, nullptr, 0, s, w.prof);
-    // W = Y - 1/2 V Z (in place)
-    ZGemm gw = zgemm_args(m, kb, kb, zop(w.V, w.vmax, 1), zop(w.S2, 64, 0), w.W, w.nmax, 1,
-                          make_double2(-0.5, 0.0), one);
-    zgemm(gw, nullptr, 0, s, w.prof);
-    // A22 -= [V W] [W V]^H on the lower triangle
-    ZGemm g1 = zgemm_args(m, m, 2 * kb, zop(w.V, w.vmax, 1), zop(w.W, w.nmax, 0, 1), A22, lda, 1,
-                          make_double2(-1.0, 0.0), one);
-    g1.kcat = kb;
-    g1.A2 = zop(w.W, w.nmax, 1);
-    g1.B2 = zop(w.V, w.vmax, 0, 1);
-    g1.lower_only = 1;
-    zgemm(g1, nullptr, 0, s, w.prof);
+  const cplx mone = make_double2(-1.0, 0.0);
+  constexpr int KG = HB_GROUP * HB;
+  const long ld = w.nmax;                      // accumulator rows, offset by the group base
+  cplx* Vg = w.acc;                            // ld x KG
+  cplx* Wg = w.acc + ld * KG;                  // ld x KG
+  cplx* Pw = w.acc + 2 * ld * KG;              // KG x HB row-major: Wg^H V
+  cplx* Pv = Pw + (long)KG * HB;               // KG x HB row-major: Vg^H V
+  int p = 0, i0 = 0;
+  while (i0 + HB < n - 1) {
+    const int base = i0 + HB;                  // first row of the group's reflectors
+    int ka = 0;
+    for (int g = 0; g < HB_GROUP && i0 + HB < n - 1; ++g, ++p, i0 += HB) {
+      const int o = i0 + HB;
+      const int m = n - o;
+      const int kb = std::min(HB, m);
+      cplx* T = w.T1 + (long)p * 4096;
+      cplx* A22 = A + (long)o * lda + o;
+      if (ka > 0) {
+        // columns i0..i0+HB-1 (rows i0..n-1) receive the group's earlier updates
+        const long r0 = i0 - base;
+        ZGemm gc = zgemm_args(n - i0, HB, 2 * ka, zop(Vg + r0, ld, 1), zop(Wg + r0, ld, 0, 1),
+                              A + (long)i0 * lda + i0, lda, 1, mone, one);
+        gc.kcat = ka;
+        gc.A2 = zop(Wg + r0, ld, 1);
+        gc.B2 = zop(Vg + r0, ld, 0, 1);
+        zgemm(gc, nullptr, 0, s, w.prof);
+      }
+      // panel QR; the explicit V (m x kb) lands in column ka of Vg
+      cplx* V = Vg + (long)ka * ld + (o - base);
+      cplx* W = Wg + (long)ka * ld + (o - base);
+      LinalgWork wp = w;
+      wp.T = T;
+      wp.V = V;
+      wp.vmax = ld;
+      qr_factor(m, HB, A + (long)i0 * lda + o, 1, lda, wp, s);
+      // X = A22 V (row-major, ld 64) from the stored lower triangle
+      ZGemm gx = zgemm_args(m, kb, m, zop(A22, lda, 1), zop(V, ld, 1), w.X2, 64, 0, one, zero);
+      gx.herm_a = 1;
+      zgemm(gx, w.gpart, w.gpart_elems, s, w.prof);
+      if (ka > 0) {
+        const long r0 = o - base;
+        ZGemm gpw = zgemm_args(ka, kb, m, zop(Wg + r0, ld, 0, 1), zop(V, ld, 1), Pw, HB, 0, one,
+                               zero);
+        zgemm(gpw, w.gpart, w.gpart_elems, s, w.prof);
+        ZGemm gpv = zgemm_args(ka, kb, m, zop(Vg + r0, ld, 0, 1), zop(V, ld, 1), Pv, HB, 0, one,
+                               zero);
+        zgemm(gpv, w.gpart, w.gpart_elems, s, w.prof);
+        ZGemm gxc = zgemm_args(m, kb, 2 * ka, zop(Vg + r0, ld, 1), zop(Pw, HB, 0), w.X2, 64, 0, mone,
+                               one);
+        gxc.kcat = ka;
+        gxc.A2 = zop(Wg + r0, ld, 1);
+        gxc.B2 = zop(Pv, HB, 0);
+        zgemm(gxc, nullptr, 0, s, w.prof);
+      }
+      // Y = X T (column-major, in column ka of Wg)
+      ZGemm gy = zgemm_args(m, kb, kb, zop(w.X2, 64, 0), zop(T, 64, 0), W, ld, 1, one, zero);
+      zgemm(gy, nullptr, 0, s, w.prof);
+      // S = V^H Y, Z = T^H S
+      ZGemm gs = zgemm_args(kb, kb, m, zop(V, ld, 0, 1), zop(W, ld, 1), w.S, 64, 0, one, zero);
+      zgemm(gs, w.gpart, w.gpart_elems, s, w.prof);
+      ZGemm gz = zgemm_args(kb, kb, kb, zop(T, 64, 1, 1), zop(w.S, 64, 0), w.S2, 64, 0, one, zero);
+      zgemm(gz, nullptr, 0, s, w.prof);
+      // W = Y - 1/2 V Z (in place)
+      ZGemm gw = zgemm_args(m, kb, kb, zop(V, ld, 1), zop(w.S2, 64, 0), W, ld, 1,
+                            make_double2(-0.5, 0.0), one);
+      zgemm(gw, nullptr, 0, s, w.prof);
+      ka += kb;
+    }
+    // trailing matrix from the next panel's first column: A22 -= [Vg Wg] [Wg Vg]^H
+    const int o2 = i0;
+    const int m2 = n - o2;
+    if (m2 > 0) {
+      const long r0 = o2 - base;
+      cplx* A22 = A + (long)o2 * lda + o2;
+      ZGemm g1 = zgemm_args(m2, m2, 2 * ka, zop(Vg + r0, ld, 1), zop(Wg + r0, ld, 0, 1), A22, lda, 1,
+                            mone, one);
+      g1.kcat = ka;
+      g1.A2 = zop(Wg + r0, ld, 1);
+      g1.B2 = zop(Vg + r0, ld, 0, 1);
+      g1.lower_only = 1;
+      zgemm(g1, nullptr, 0, s, w.prof);
+    }
   }
 }
 

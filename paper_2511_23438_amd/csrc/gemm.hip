@@ -571,6 +571,160 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
 }
 
 // Sum the split-K partials and apply the store epilogue.
+// ---------------------------------------------------------------------------
+// Hermitian operand (lower triangle stored column-major) times a narrow
+// operand of at most 32 columns: 128 x 32 outputs per workgroup, each wave
+// 32 x 32 as 2 x 2 MFMA blocks, so that a wave issues as many products per
+// staged K-tile as in the square tile (the 64 x 32 narrow layout issues half).
+#define HM 128
+#define HN 32
+
+template <int TB>
+__global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
+  const ZGemm& g = gd.g;
+  __shared__ double As[3][BK][HM];
+  __shared__ double Bs[3][BK][HN];
+  const int n0 = blockIdx.x * HN, m0 = blockIdx.y * HM;
+  const int bz = blockIdx.z;
+  const int bat = bz / gd.ksplit, ks = bz % gd.ksplit;
+  const cplx* A = g.A.p + (long)bat * g.A.stride;
+  const cplx* B = g.B.p + (long)bat * g.B.stride;
+  const long lda = g.A.ld, ldb = g.B.ld;
+  const long kbeg = (long)ks * gd.kchunk;
+  long kend = kbeg + gd.kchunk;
+  if (kend > g.K) kend = g.K;
+  const long mlast = g.M - 1, nlast = g.N - 1;
+
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int wr = w * 32;
+  d4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      t1[a][b] = (d4){0, 0, 0, 0};
+      t2[a][b] = (d4){0, 0, 0, 0};
+      t3[a][b] = (d4){0, 0, 0, 0};
+    }
+
+  // A tile element u of this thread: below-diagonal tiles take 8 consecutive
+  // rows of one column (t & 15 picks the row group, t >> 4 the column); tiles
+  // wholly above the diagonal read the stored transpose, 8 consecutive k of
+  // one row (t >> 1 the row, t & 1 the k group)
+  auto a_coords = [&](long k0, int u, long& gi, long& gk) {
+    if (k0 < (long)m0 + HM) {
+      gk = k0 + (t >> 4);
+      gi = m0 + (t & 15) * 8 + u;
+    } else {
+      gi = m0 + (t >> 1);
+      gk = k0 + (t & 1) * 8 + u;
+    }
+  };
+  auto b_coords = [&](long k0, int u, long& gk, long& gj) {
+    if (TB == 0) {
+      gk = k0 + (t >> 4);
+      gj = n0 + (t & 15) * 2 + u;
+    } else {
+      gj = n0 + (t >> 3);
+      gk = k0 + (t & 7) * 2 + u;
+    }
+  };
+  auto load = [&](long k0, cplx ra[8], cplx rb[2]) {
+    const long klast = kend - 1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      long gi, gk;
+      a_coords(k0, u, gi, gk);
+      const long ci = min(gi, mlast), ck = min(gk, klast);
+      ra[u] = A[(ci >= ck) ? ck * lda + ci : ci * lda + ck];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      long gk, gj;
+      b_coords(k0, u, gk, gj);
+      const long ck = min(gk, klast), cj = min(gj, nlast);
+      rb[u] = B[TB == 0 ? ck * ldb + cj : cj * ldb + ck];
+    }
+  };
+
+  cplx ra[8], rb[2];
+  if (kbeg < kend) load(kbeg, ra, rb);
+  const double sgb = g.B.conj ? -1.0 : 1.0;
+  for (long k0 = kbeg; k0 < kend; k0 += BK) {
+    // mirror, zero out-of-range elements, stage the three planes
+    const bool lower = k0 < (long)m0 + HM;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      long gi, gk;
+      a_coords(k0, u, gi, gk);
+      cplx v = ra[u];
+      if (gi < gk) v.y = -v.y;
+      if (gi == gk) v.y = 0.0;
+      ra[u] = (gi < g.M && gk < kend) ? v : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      long gk, gj;
+      b_coords(k0, u, gk, gj);
+      rb[u] = (gj < g.N && gk < kend) ? rb[u] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int ii = lower ? (t & 15) * 8 + u : (t >> 1);
+      const int kk = lower ? (t >> 4) : (t & 1) * 8 + u;
+      As[0][kk][ii] = ra[u].x;
+      As[1][kk][ii] = ra[u].y;
+      As[2][kk][ii] = ra[u].x + ra[u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int jj = TB == 0 ? (t & 15) * 2 + u : (t >> 3);
+      const int kk = TB == 0 ? (t >> 4) : (t & 7) * 2 + u;
+      const double re = rb[u].x, im = sgb * rb[u].y;
+      Bs[0][kk][jj] = re;
+      Bs[1][kk][jj] = im;
+      Bs[2][kk][jj] = re + im;
+    }
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK, ra, rb);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (l >> 4);
+      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = As[0][kr][wr + a * 16 + (l & 15)];
+        ai[a] = As[1][kr][wr + a * 16 + (l & 15)];
+        as[a] = As[2][kr][wr + a * 16 + (l & 15)];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        br[b] = Bs[0][kr][b * 16 + (l & 15)];
+        bi[b] = Bs[1][kr][b * 16 + (l & 15)];
+        bs[b] = Bs[2][kr][b * 16 + (l & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], t1[a][b], 0, 0, 0);
+          t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], t2[a][b], 0, 0, 0);
+          t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[a], bs[b], t3[a][b], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + b * 16 + (l & 15),
+                  make_double2(t1[a][b][v] - t2[a][b][v],
+                               t3[a][b][v] - t1[a][b][v] - t2[a][b][v]));
+}
+
 __global__ void zgemm_reduce(ZGemmDev gd) {
   const ZGemm& g = gd.g;
   long total = (long)g.M * g.N;
@@ -654,9 +808,33 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     else hipLaunchKernelGGL((KER<1, 1>), grid, dim3(256), 0, s, gd);                         \
   } while (0)
   const bool narrow = g.N <= 32 && g.epi == EPI_STORE;
+  if (g.herm_a && narrow) {
+    // 128 x 32 tiles; split K until about 1024 workgroups run
+    const long htiles = (long)ceil_div(g.M, HM) * g.batch;
+    ZGemmDev hd = gd;
+    hd.ksplit = 1;
+    hd.kchunk = g.K;
+    if (partial && g.K >= 1024) {
+      int ks = (int)std::min<long>(g.K / 256, (1024 + htiles - 1) / htiles);
+      while (ks > 1 && (long)ks * g.batch * g.M * g.N > partial_elems) --ks;
+      if (ks > 1) {
+        hd.kchunk = ((g.K + ks - 1) / ks + BK2 - 1) / BK2 * BK2;
+        hd.ksplit = (int)((g.K + hd.kchunk - 1) / hd.kchunk);
+      }
+    }
+    dim3 hgrid(1, ceil_div(g.M, HM), g.batch * hd.ksplit);
+    if (tb == 1) hipLaunchKernelGGL((zhemm_n32_kernel<1>), hgrid, dim3(256), 0, s, hd);
+    else hipLaunchKernelGGL((zhemm_n32_kernel<0>), hgrid, dim3(256), 0, s, hd);
+    if (hd.ksplit > 1) {
+      long total = (long)g.M * g.N;
+      int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+      hipLaunchKernelGGL(zgemm_reduce, dim3(blocks, g.batch), dim3(256), 0, s, hd);
+    }
+    if (prof) prof->end(pk, flops, s);
+    return;
+  }
   if (g.herm_a) {
-    if (narrow && tb == 1) hipLaunchKernelGGL((zgemm_kernel<2, 1, 1>), grid, dim3(256), 0, s, gd);
-    else if (tb == 0) hipLaunchKernelGGL((zgemm_kernel<2, 0>), grid, dim3(256), 0, s, gd);
+    if (tb == 0) hipLaunchKernelGGL((zgemm_kernel<2, 0>), grid, dim3(256), 0, s, gd);
     else hipLaunchKernelGGL((zgemm_kernel<2, 1>), grid, dim3(256), 0, s, gd);
   } else if (narrow && g.prec == GEMM_F64) {
     if (ta == 0 && tb == 0) hipLaunchKernelGGL((zgemm_kernel<0, 0, 1>), grid, dim3(256), 0, s, gd);

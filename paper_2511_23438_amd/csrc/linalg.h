@@ -61,6 +61,7 @@ struct LinalgWork {
   cplx* T1 = nullptr;       // stage-1 panel block factors, (nmax/TRD_NB + 1) * 4096
   cplx* X2 = nullptr;       // nmax x 64 (row-major)
   cplx* S2 = nullptr;       // 64 x 64
+  cplx* acc = nullptr;      // stage-1 reflectors of a panel group, he2hb_acc_elems(nmax)
   cplx* Ab = nullptr;       // band, nmax x (2*TRD_NB + 1), bulge-chased in place
   cplx* Br = nullptr;       // row-major copy of the band before chasing
   cplx* Ubuf = nullptr;     // inverse-iteration U rows, band_invit_work_elems()
@@ -127,6 +128,13 @@ long band_invit_work_elems(long n, int q);
 // Destroys the captured graphs and the capture stream of `w`.
 void linalg_release(LinalgWork& w);
 constexpr int BAND_W = 2 * TRD_NB + 1;
+// stage-1 panels whose reflectors are accumulated before the trailing update
+constexpr int HB_GROUP = 4;
+// accumulated V and W (nmax x HB_GROUP*TRD_NB each, column-major) and the two
+// small products of a panel with them
+inline long he2hb_acc_elems(long nmax) {
+  return 2 * nmax * HB_GROUP * TRD_NB + 2L * HB_GROUP * TRD_NB * TRD_NB;
+}
 
 // Top-q eigenspace of Hermitian G (n x n column-major, overwritten): an
 // orthonormal basis U (n x q row-major, ld ldu) ordered by descending

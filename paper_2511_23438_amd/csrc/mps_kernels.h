@@ -6,6 +6,11 @@ namespace mpsim {
 
 // A[a, s, b] <- sum_t U[s, t] A[a, t, b] for a site of shape (b0, d, b1).
 void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream_t s);
+// dst = one site of the rank-2 operator of exp(-i phi Z Z') on a span of
+// sites (mode 0 first, 1 inside, 2 last); c = cos(phi), sn = sin(phi); the
+// doubled bonds take index 2 * old + k
+void launch_mpo_site(const cplx* src, cplx* dst, int b0, int d, int b1, int mode, int w, int bit,
+                     double c, double sn, hipStream_t s);
 // dst[slot] = sum |x|^2 over len entries (deterministic two-pass reduction).
 void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStream_t s);
 // Truncation bookkeeping: f = sc[3]/sc[2], sc[0] += log f, sc[4] = 1/sqrt(sc[3]),

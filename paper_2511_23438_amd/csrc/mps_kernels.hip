@@ -26,6 +26,48 @@ __global__ __launch_bounds__(256) void k_apply_u1(cplx* site, int b0, int d, int
   }
 }
 
+// One site of the rank-2 operator exp(-i phi Z Z') = cos(phi) I I - i sin(phi) Z Z'
+// on the span of sites between the two qubits; the operator index k joins
+// the doubled bonds (new index 2 * old + k). mode 0: first site, the right
+// bond gains k with weights cos(phi) and -i sin(phi) z(s); mode 1: inside,
+// k passes through unchanged; mode 2: last site, the left bond gains k with
+// weights 1 and z(s). z(s) = +1 / -1 for bit `bit` (0 = most significant of
+// w bits) of the fused index s equal to 0 / 1.
+__global__ void k_mpo_site(const cplx* src, cplx* dst, int b0, int d, int b1, int mode, int w,
+                           int bit, double c, double sn) {
+  const long ob0 = mode == 0 ? b0 : 2L * b0, ob1 = mode == 2 ? b1 : 2L * b1;
+  const long total = ob0 * d * ob1;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long oc = idx % ob1;
+    const long rest = idx / ob1;
+    const int sidx = (int)(rest % d);
+    const long oa = rest / d;
+    const double z = 1.0 - 2.0 * ((sidx >> (w - 1 - bit)) & 1);
+    cplx v;
+    if (mode == 0) {
+      const int k = (int)(oc & 1);
+      v = src[(oa * d + sidx) * b1 + (oc >> 1)];
+      v = k == 0 ? cscale(v, c) : cmul(make_double2(0.0, -sn * z), v);
+    } else if (mode == 1) {
+      const bool same = (oa & 1) == (oc & 1);
+      v = same ? src[((oa >> 1) * d + sidx) * b1 + (oc >> 1)] : make_double2(0.0, 0.0);
+    } else {
+      v = src[((oa >> 1) * d + sidx) * b1 + oc];
+      if (oa & 1) v = cscale(v, z);
+    }
+    dst[idx] = v;
+  }
+}
+
+void launch_mpo_site(const cplx* src, cplx* dst, int b0, int d, int b1, int mode, int w, int bit,
+                     double c, double sn, hipStream_t s) {
+  const long total = (mode == 0 ? b0 : 2L * b0) * (long)d * (mode == 2 ? b1 : 2L * b1);
+  const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_mpo_site, dim3(std::max(blocks, 1)), dim3(256), 0, s, src, dst, b0, d, b1, mode,
+                     w, bit, c, sn);
+}
+
 void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream_t s) {
   long pairs = (long)b0 * b1;
   int blocks = (int)std::min<long>((pairs + 255) / 256, 4096);

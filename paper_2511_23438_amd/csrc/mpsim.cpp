@@ -120,21 +120,37 @@ Sizes plan_sizes(const Plan& p) {
   z.eig_path = p.eig_path;
   const long D = p.dmax;
   for (int s = 0; s < p.N; ++s) {
-    long e = (long)p.cap[s] * D * p.cap[s + 1];
+    long e = (long)p.xcap[s] * D * p.xcap[s + 1];
     z.site_max = std::max(z.site_max, e);
     z.sites_total += e;
-    z.mmax = std::max(z.mmax, std::max((long)p.cap[s] * D, D * p.cap[s + 1]));
-    z.colmax = std::max(z.colmax, (long)std::max(p.cap[s], p.cap[s + 1]));
+    z.mmax = std::max(z.mmax, std::max((long)p.xcap[s] * D, D * p.xcap[s + 1]));
+    z.colmax = std::max(z.colmax, (long)std::max(p.xcap[s], p.xcap[s + 1]));
   }
-  for (int i = 0; i + 1 < p.N; ++i) {
-    long mo = (long)p.cap[i] * D, no = D * p.cap[i + 2];
-    z.theta = std::max(z.theta, mo * no);
-    long kg = std::min(mo, no);
-    z.gram = std::max(z.gram, kg * kg);
-    z.nmax = std::max(z.nmax, kg);
-    z.qmax = std::max(z.qmax, std::min<long>(p.chi, kg));
+  if (p.schedule == 4) {
+    // bond truncations: the site (cap D) x (2 cap) and its Gram on the smaller
+    // side; C = (kept) x (2 cap)
+    for (int b = 1; b < p.N; ++b) {
+      long kg = std::min((long)p.cap[b - 1] * D, (long)p.xcap[b]);
+      z.theta = std::max(z.theta, (long)p.cap[b] * p.xcap[b]);
+      z.gram = std::max(z.gram, kg * kg);
+      z.nmax = std::max(z.nmax, kg);
+      z.qmax = std::max(z.qmax, std::min<long>(p.chi, kg));
+    }
+  } else {
+    for (int i = 0; i + 1 < p.N; ++i) {
+      long mo = (long)p.cap[i] * D, no = D * p.cap[i + 2];
+      z.theta = std::max(z.theta, mo * no);
+      long kg = std::min(mo, no);
+      z.gram = std::max(z.gram, kg * kg);
+      z.nmax = std::max(z.nmax, kg);
+      z.qmax = std::max(z.qmax, std::min<long>(p.chi, kg));
+    }
   }
-  // bond spectrum Gram (cap x cap) also fits: cap <= kg bound
+  // bond spectrum Gram (cap x cap)
+  for (int b = 1; b < p.N; ++b) {
+    z.nmax = std::max(z.nmax, (long)p.cap[b]);
+    z.gram = std::max(z.gram, (long)p.cap[b] * p.cap[b]);
+  }
   z.mmax = std::max(z.mmax, z.nmax);
   z.colmax = std::max(z.colmax, z.qmax);
   // the two-stage panels factor TRD_NB columns at a time
@@ -149,7 +165,7 @@ Sizes plan_sizes(const Plan& p) {
 
 struct LwSizes {
   long W, tpart, P, dpart, npart, iwork, T, V, W12, gpart;
-  long T1, X2, band, ubuf;  // two-stage path (zero when it is never taken)
+  long T1, X2, band, ubuf, acc;  // two-stage path (zero when it is never taken)
 };
 
 // whether a Gram side of n takes the two-stage eigensolver
@@ -171,12 +187,13 @@ LwSizes lw_sizes(const Sizes& z) {
   l.V = std::max(z.nmax, z.mmax) * 64;
   l.W12 = 64 * z.colmax;
   l.gpart = 4L << 20;
-  l.T1 = l.X2 = l.band = l.ubuf = 0;
+  l.T1 = l.X2 = l.band = l.ubuf = l.acc = 0;
   if (use_two_stage(z.eig_path, z.nmax)) {
     l.T1 = (z.nmax / TRD_NB + 2) * 4096;
     l.X2 = z.nmax * 64;
     l.band = z.nmax * BAND_W;
     l.ubuf = band_invit_work_elems(z.nmax, (int)z.qmax);
+    l.acc = he2hb_acc_elems(z.nmax);
   }
   return l;
 }
@@ -189,7 +206,7 @@ size_t footprint(const Plan& p) {
   total += (size_t)z.sites_total * c;
   total += (size_t)(z.theta + z.gram + 3 * z.tmp + 2 * z.env + z.envx) * c;
   total += (size_t)(l.W + l.tpart + l.P + l.dpart + l.T + 4096 + 2 * l.W12 + l.V + l.gpart) * c;
-  total += (size_t)(l.T1 + l.X2 + 4096 + 2 * l.band + l.ubuf) * c;
+  total += (size_t)(l.T1 + l.X2 + 4096 + 2 * l.band + l.ubuf + l.acc) * c;
   total += (size_t)(l.npart + l.iwork + 4 * z.nmax + z.qmax + 2 + 16 + 2 * 4096) * d;
   total += (size_t)(z.nmax + z.colmax) * c;
   return total;
@@ -375,6 +392,100 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   if (swap) std::swap(h->pos[i], h->pos[i + 1]);
 }
 
+// Truncate the bond between sites i and i+1 with the orthogonality centre on
+// site i and every site right of it right-orthonormal: the site M
+// ((b d) x b') keeps the top q = min(chi, rank bound, b d, b') singular
+// directions of the bond (results section: the centre is moved onto the bond
+// before the decomposition, so its cost depends on the bond only). The Gram
+// matrix is taken on the smaller side; on the column side the kept part
+// M V = Q R' is re-orthonormalised by QR, site i <- Q, and R' V^H moves into
+// site i+1, which becomes the centre.
+void truncate_bond(mps_sim* h, int i) {
+  const Plan& p = h->plan;
+  hipStream_t s = h->stream;
+  const int b0 = h->bond[i], d = p.dim(h->pos[i]), k = h->bond[i + 1];
+  const int d2 = p.dim(h->pos[i + 1]), b2 = h->bond[i + 2];
+  const long m = (long)b0 * d, n2 = (long)d2 * b2;
+  const int q = (int)std::min<long>(std::min<long>(p.chi, p.rank_cap[i + 1]), std::min<long>(m, k));
+  const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
+  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->nupdates;
+  cplx* M = h->site[i];
+  norm2(h, M, m * k, 2);
+  ensure_log(h, h->nlog + 1);
+  if (m < k) {
+    const int kg = (int)m;
+    const int extra = (q < kg) ? 1 : 0;
+    ZGemm gg = zgemm_args(kg, kg, k, zop(M, k, 0), zop(M, k, 1, 1), h->gram, kg, 1, one, zero);
+    gg.lower_only = 1;
+    gg.tag = PROF_GRAM;
+    zgemm(gg, nullptr, 0, s, &h->prof);
+    heev(h, kg, q, h->tmpB, seed);
+    // C = U^H M (q x k)
+    ZGemm gc = zgemm_args(q, k, kg, zop(h->tmpB, q, 1, 1), zop(M, k, 0), h->theta, k, 0, one, zero);
+    zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
+    norm2(h, h->theta, (long)q * k, 3);
+    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    HIPCHK(hipMemcpyAsync(M, h->tmpB, sizeof(cplx) * (size_t)m * q, hipMemcpyDeviceToDevice, s));
+  } else {
+    const int kg = k;
+    const int extra = (q < kg) ? 1 : 0;
+    ZGemm gg = zgemm_args(kg, kg, (int)m, zop(M, k, 1, 1), zop(M, k, 0), h->gram, kg, 1, one, zero);
+    gg.lower_only = 1;
+    gg.tag = PROF_GRAM;
+    zgemm(gg, nullptr, 0, s, &h->prof);
+    heev(h, kg, q, h->tmpB, seed);
+    // X = M V (m x q), kept weight |X|^2
+    ZGemm gx = zgemm_args((int)m, q, kg, zop(M, k, 0), zop(h->tmpB, q, 0), h->tmpA, q, 0, one, zero);
+    zgemm(gx, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
+    norm2(h, h->tmpA, m * q, 3);
+    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    // X = Q R': site i <- Q, C = R' V^H (q x k)
+    qr_factor((int)m, q, h->tmpA, q, 1, h->lw, s);
+    qr_form_q((int)m, q, h->tmpA, q, 1, h->lw, M, q, s);
+    qr_get_r((int)m, q, h->tmpA, q, 1, h->tmpC, q, s);
+    ZGemm gc = zgemm_args(q, k, q, zop(h->tmpC, q, 0), zop(h->tmpB, q, 1, 1), h->theta, k, 0, one, zero);
+    zgemm(gc, nullptr, 0, s, &h->prof);
+  }
+  launch_scale_by(h->theta, (long)q * k, h->dscal, s);
+  // site i+1 <- C * site i+1 (q x d2 b2)
+  ZGemm gn = zgemm_args(q, (int)n2, k, zop(h->theta, k, 0), zop(h->site[i + 1], n2, 0), h->tmpA, n2, 0,
+                        one, zero);
+  gn.prec = h->gprec;
+  zgemm(gn, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
+  HIPCHK(hipMemcpyAsync(h->site[i + 1], h->tmpA, sizeof(cplx) * (size_t)q * n2, hipMemcpyDeviceToDevice, s));
+  h->nlog += 1;
+  h->nupdates += 1;
+  h->bond[i + 1] = q;
+  h->centre = i + 1;
+}
+
+// One ZZ gate exp(-i J dt Z Z') between bit ja of the block at site sa and
+// bit jb of the block at site sb > sa, applied as a rank-2 matrix product
+// operator (results section: a gate between two blocks doubles every bond
+// between them), then canonical form again (LQ steps from sb down to sa) and
+// truncation of the doubled bonds from left to right.
+void zz_mpo(mps_sim* h, int sa, int sb, int ja, int jb) {
+  const Plan& p = h->plan;
+  hipStream_t s = h->stream;
+  move_centre(h, sa);
+  const double phi = p.J * p.dt;
+  const double c = std::cos(phi), sn = std::sin(phi);
+  for (int t = sa; t <= sb; ++t) {
+    const int blk = h->pos[t];
+    const int b0 = h->bond[t], d = p.dim(blk), b1 = h->bond[t + 1];
+    const int mode = (t == sa) ? 0 : (t == sb ? 2 : 1);
+    const int bit = (t == sa) ? ja : jb;
+    launch_mpo_site(h->site[t], h->tmpA, b0, d, b1, mode, p.block_width[blk], bit, c, sn, s);
+    const long ob0 = mode == 0 ? b0 : 2L * b0, ob1 = mode == 2 ? b1 : 2L * b1;
+    HIPCHK(hipMemcpyAsync(h->site[t], h->tmpA, sizeof(cplx) * (size_t)(ob0 * d * ob1),
+                          hipMemcpyDeviceToDevice, s));
+  }
+  for (int b = sa + 1; b <= sb; ++b) h->bond[b] *= 2;
+  h->centre = sb;
+  move_centre(h, sa);
+  for (int t = sa; t < sb; ++t) truncate_bond(h, t);
+}
+
 void single_site(mps_sim* h, int site, int variant) {
   const Plan& p = h->plan;
   const int b = h->pos[site];
@@ -387,7 +498,7 @@ void run_step(mps_sim* h) {
   std::vector<int> pos = h->pos;
   h->plan.step_ops(pos, ops);
   int nu2 = 0, done = 0;
-  for (const Op& o : ops) nu2 += (o.kind == 1);
+  for (const Op& o : ops) nu2 += (o.kind == 1 || o.kind == 3);
   for (size_t k = 0; k < ops.size(); ++k) {
     const Op& o = ops[k];
     if (o.kind == 1) {
@@ -395,6 +506,10 @@ void run_step(mps_sim* h) {
       for (size_t k2 = k + 1; k2 < ops.size(); ++k2)
         if (ops[k2].kind == 1) { next = ops[k2].site; break; }
       two_site(h, o.site, o.swap, o.gate, next);
+      ++done;
+      if (h->progress) h->progress(h->progress_ctx, h->steps, done, nu2);
+    } else if (o.kind == 3) {
+      zz_mpo(h, o.site, o.site_b, o.bit_a, o.bit_b);
       ++done;
       if (h->progress) h->progress(h->progress_ctx, h->steps, done, nu2);
     } else {
@@ -511,6 +626,8 @@ mps_status mps_schedule_dump(const mps_config* cfg, int32_t nsteps, int32_t* ops
     int32_t* r = ops + 6 * k;
     if (o.kind == 1) {
       r[0] = 1; r[1] = o.site; r[2] = o.swap; r[3] = o.gate; r[4] = o.block_a; r[5] = o.block_b;
+    } else if (o.kind == 3) {
+      r[0] = 3; r[1] = o.site; r[2] = o.site_b; r[3] = o.bit_a; r[4] = o.bit_b; r[5] = 0;
     } else {
       r[0] = 2; r[1] = o.site; r[2] = o.variant; r[3] = o.block_a; r[4] = 0; r[5] = 0;
     }
@@ -542,7 +659,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     Sizes z = plan_sizes(p);
     LwSizes l = lw_sizes(z);
     h->site.resize(p.N);
-    for (int s = 0; s < p.N; ++s) h->site[s] = dalloc<cplx>(h, (long)p.cap[s] * p.dmax * p.cap[s + 1]);
+    for (int s = 0; s < p.N; ++s) h->site[s] = dalloc<cplx>(h, (long)p.xcap[s] * p.dmax * p.xcap[s + 1]);
     h->theta = dalloc<cplx>(h, z.theta);
     h->gram = dalloc<cplx>(h, z.gram);
     h->tmpA = dalloc<cplx>(h, z.tmp);
@@ -593,6 +710,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
       w.Ab = dalloc<cplx>(h, l.band);
       w.Br = dalloc<cplx>(h, l.band);
       w.Ubuf = dalloc<cplx>(h, l.ubuf);
+      w.acc = dalloc<cplx>(h, l.acc);
     }
     // gate tables
     long off = 0;
@@ -812,6 +930,8 @@ mps_status mps_set_state(mps_handle h, const int32_t* bonds, const double* const
 mps_status mps_apply_two_site(mps_handle h, int32_t site, int32_t swap, int32_t gate) {
   GUARD(h);
   if (site < 0 || site + 1 >= h->plan.N) return fail(h, MPS_E_INVAL, "bad site");
+  if (h->plan.schedule == 4)
+    return fail(h, MPS_E_UNSUPPORTED, "two-site updates are not sized for the gate-by-gate schedule");
   TRYDEV(h, two_site(h, site, swap ? 1 : 0, gate ? 1 : 0, -1); HIPCHK(hipGetLastError()));
   return MPS_OK;
 }

@@ -9,6 +9,7 @@
 #include "planner.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <set>
 
@@ -21,7 +22,7 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   if (cfg->layers >= 2) {
     if (cfg->rows < 1 || cfg->cols < 1) { *msg = "cube extents must be >= 1"; return MPS_E_INVAL; }
     if ((long)cfg->rows * cfg->cols * cfg->layers > 256) { *msg = "cube with > 256 sites unsupported"; return MPS_E_UNSUPPORTED; }
-    if (cfg->schedule != 3) { *msg = "the cube needs schedule 3"; return MPS_E_INVAL; }
+    if (cfg->schedule != 3 && cfg->schedule != 4) { *msg = "the cube needs schedule 3 or 4"; return MPS_E_INVAL; }
   } else {
     if (cfg->rows < 1 || cfg->cols < 2) { *msg = "need rows >= 1 and cols >= 2"; return MPS_E_INVAL; }
     if (cfg->cols > 8) { *msg = "cols > 8 (block width > 4, d > 16) unsupported"; return MPS_E_UNSUPPORTED; }
@@ -31,7 +32,7 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   if (cfg->chi_max > 4096) { *msg = "chi_max > 4096 unsupported"; return MPS_E_UNSUPPORTED; }
   if (cfg->precision < 0 || cfg->precision > 2) { *msg = "bad precision"; return MPS_E_INVAL; }
   if (cfg->trotter_order != 1 && cfg->trotter_order != 2) { *msg = "trotter_order must be 1 or 2"; return MPS_E_INVAL; }
-  if (cfg->schedule < 1 || cfg->schedule > 3) { *msg = "schedule must be 1, 2 or 3"; return MPS_E_INVAL; }
+  if (cfg->schedule < 1 || cfg->schedule > 4) { *msg = "schedule must be 1, 2, 3 or 4"; return MPS_E_INVAL; }
   if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
   if (cfg->eig_path < 0 || cfg->eig_path > 2) { *msg = "eig_path must be 0, 1 or 2"; return MPS_E_INVAL; }
   if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
@@ -56,6 +57,38 @@ void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
     o.kind = 2; o.site = site; o.variant = variant; o.block_a = pos[site]; o.block_b = -1;
     out.push_back(o);
   };
+  if (schedule == 4) {
+    // gate by gate: every ZZ bond between two blocks is its own gate, a
+    // rank-2 operator on the span of sites between them; blocks never move.
+    // Order: (first site, second site, bit in the first block, bit in the
+    // second block).
+    if (order == 2)
+      for (int p = 0; p < N; ++p) u1(p, 1);
+    std::vector<int> where(nb, 0), blk_of(n, 0), idx_in(n, 0);
+    for (int p = 0; p < N; ++p) where[pos[p]] = p;
+    for (int b = 0; b < nb; ++b)
+      for (size_t j = 0; j < block_qubits[b].size(); ++j) {
+        blk_of[block_qubits[b][j]] = b;
+        idx_in[block_qubits[b][j]] = (int)j;
+      }
+    std::vector<std::array<int, 4>> gates;
+    for (auto& bd : bonds) {
+      int a = blk_of[bd.first], b = blk_of[bd.second];
+      if (a == b) continue;
+      int sa = where[a], sb = where[b], ja = idx_in[bd.first], jb = idx_in[bd.second];
+      if (sa > sb) { std::swap(sa, sb); std::swap(ja, jb); }
+      gates.push_back({sa, sb, ja, jb});
+    }
+    std::sort(gates.begin(), gates.end());
+    for (auto& gt : gates) {
+      Op o{};
+      o.kind = 3; o.site = gt[0]; o.site_b = gt[1]; o.bit_a = gt[2]; o.bit_b = gt[3];
+      o.block_a = pos[gt[0]]; o.block_b = pos[gt[1]];
+      out.push_back(o);
+    }
+    for (int p = 0; p < N; ++p) u1(p, order == 1 ? 0 : 2);
+    return;
+  }
   if (schedule == 3) {
     // route and return: coupled pairs in the order of their chain positions
     // at the start of the step; the block at pb travels to pa+1 by SWAP
@@ -283,6 +316,20 @@ void build_plan(const mps_config* cfg, Plan& p) {
                                                    std::pow((double)p.dmax, p.N - b)));
     p.cap[b] = (int)lim;
   }
+  // rank bound of each bond in the start order (blocks keep their sites
+  // under schedule 4): the smaller product of local dimensions on its sides
+  p.rank_cap.assign(p.N + 1, 1);
+  for (int b = 1; b < p.N; ++b) {
+    double left = 1, right = 1;
+    for (int s = 0; s < b; ++s) left *= p.dim(p.snake_order[s]);
+    for (int s = b; s < p.N; ++s) right *= p.dim(p.snake_order[s]);
+    p.rank_cap[b] = (long)std::min(std::min(left, right), 1e15);
+  }
+  // bonds between the two blocks of a schedule-4 gate double before they
+  // are truncated again
+  p.xcap = p.cap;
+  if (p.schedule == 4)
+    for (int b = 1; b < p.N; ++b) p.xcap[b] = 2 * p.cap[b];
 }
 
 }  // namespace mpsim

@@ -13,12 +13,13 @@ namespace mpsim {
 typedef std::complex<double> zc;
 
 struct Op {          // one entry of the step schedule
-  int kind;          // 1 = two-site update, 2 = single-site gate
+  int kind;          // 1 = two-site update, 2 = single-site gate, 3 = ZZ gate as a rank-2 MPO
   int site;
   int swap;          // kind 1
   int gate;          // kind 1: block-pair phase applied
   int variant;       // kind 2
   int block_a, block_b;  // blocks at site, site+1 before the op (kind 1); block (kind 2)
+  int site_b, bit_a, bit_b;  // kind 3: sites site < site_b, bit of each block's fused index
 };
 
 struct Plan {
@@ -31,6 +32,8 @@ struct Plan {
   int wL = 0, wR = 0, dmax = 1;
   std::vector<int> block_width;               // per block id
   std::vector<int> cap;                       // bond caps b_0..b_N
+  std::vector<int> xcap;                      // transient caps: 2 cap inside the chain for schedule 4
+  std::vector<long> rank_cap;                 // smaller Hilbert-space dimension on either side of a bond
   std::vector<std::vector<int>> block_qubits; // per block, in column order
   std::vector<std::pair<int, int>> bonds;     // ZZ bonds (q1 < q2), each once
 

@@ -123,7 +123,9 @@ def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
                 precision: str = "fp64", periodic: bool = True, seed: int = 0,
                 schedule: int = 1, eig_path: int = 0, layers: int = 0) -> MpsConfig:
     """rows x cols grid with half-row blocks, or with layers >= 2 the
-    rows x cols x layers cube with one qubit per site (schedule 3)."""
+    rows x cols x layers cube with one qubit per site (schedule 3 or 4).
+    schedule: 1 block pairs with routed wrap pairs, 2 rotating rows, 3 route
+    and return, 4 gate by gate (rank-2 operators and bond truncations)."""
     return MpsConfig(rows, cols, chi, PRECISION[precision], order, schedule,
                      1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0)
 

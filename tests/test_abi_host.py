@@ -32,41 +32,43 @@ def test_header_symbols_exported():
 @pytest.mark.parametrize("R,C", [(4, 4), (5, 6), (6, 8), (7, 8), (3, 3), (4, 5), (1, 4),
                                  (2, 3), (5, 5)])
 @pytest.mark.parametrize("order", [1, 2])
-@pytest.mark.parametrize("sched", [1, 2, 3])
+@pytest.mark.parametrize("sched", [1, 2, 3, 4])
 def test_schedule_equals_oracle(R, C, order, sched):
     cfg = mpsim.make_config(R, C, 16, order=order, schedule=sched)
     got = mpsim.schedule_dump(cfg, 3)
     ref = oracle_schedule(Grid(R, C), 3, order, sched)
+    _same_ops(got, ref)
+
+
+def _same_ops(got, ref):
     assert len(got) == len(ref)
     for row, op in zip(got, ref):
         if op[0] == "U2":
             assert tuple(row) == (1, op[1], op[2], op[3], op[4], op[5])
+        elif op[0] == "ZZ":
+            assert tuple(row) == (3, op[1], op[2], op[3], op[4], 0)
         else:
             assert tuple(row[:4]) == (2, op[1], op[2], op[3])
 
 
 @pytest.mark.parametrize("shape", [(2, 2, 3), (3, 3, 3), (2, 3, 4), (1, 2, 5), (4, 4, 4)])
 @pytest.mark.parametrize("order", [1, 2])
-def test_cube_schedule_equals_oracle(shape, order):
-    """Cube with one qubit per site: the C++ planner's route-and-return list
-    equals the oracle's."""
+@pytest.mark.parametrize("sched", [3, 4])
+def test_cube_schedule_equals_oracle(shape, order, sched):
+    """Cube with one qubit per site: the C++ planner's route-and-return and
+    gate-by-gate lists equal the oracle's."""
     from oracle.lattice import Cube
     lx, ly, lz = shape
-    cfg = mpsim.make_config(lx, ly, 8, order=order, schedule=3, layers=lz, periodic=False)
+    cfg = mpsim.make_config(lx, ly, 8, order=order, schedule=sched, layers=lz, periodic=False)
     got = mpsim.schedule_dump(cfg, 2)
-    ref = oracle_schedule(Cube(lx, ly, lz), 2, order, 3)
-    assert len(got) == len(ref)
-    for row, op in zip(got, ref):
-        if op[0] == "U2":
-            assert tuple(row) == (1, op[1], op[2], op[3], op[4], op[5])
-        else:
-            assert tuple(row[:4]) == (2, op[1], op[2], op[3])
+    ref = oracle_schedule(Cube(lx, ly, lz), 2, order, sched)
+    _same_ops(got, ref)
 
 
 @pytest.mark.parametrize("kw,status", [
     (dict(cols=1), mpsim.MPS_E_INVAL), (dict(rows=0), mpsim.MPS_E_INVAL),
     (dict(cols=9), mpsim.MPS_E_UNSUPPORTED), (dict(chi=0), mpsim.MPS_E_INVAL),
-    (dict(order=3), mpsim.MPS_E_INVAL), (dict(schedule=4), mpsim.MPS_E_INVAL),
+    (dict(order=3), mpsim.MPS_E_INVAL), (dict(schedule=5), mpsim.MPS_E_INVAL),
     (dict(layers=2, schedule=1), mpsim.MPS_E_INVAL),
     (dict(rows=8, cols=8, layers=8, schedule=3), mpsim.MPS_E_UNSUPPORTED)])
 def test_invalid_config_rejected(kw, status):

@@ -367,3 +367,71 @@ def test_route_return_schedule_truncating_parity(R, C, chi, seed):
     f_gpu, _ = sim.truncation_log()
     f_ora = np.array([u["f"] for u in ora.update_log])
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
+
+
+# ---- gate-by-gate path (schedule 4): each inter-block ZZ as a rank-2 MPO ----
+
+@pytest.mark.parametrize("R,C,chi,steps,order", [(3, 4, 64, 2, 1), (3, 3, 32, 2, 2),
+                                                  (4, 4, 256, 1, 1), (2, 4, 16, 3, 1)])
+def test_gate_by_gate_full_chi_matches_state_vector(R, C, chi, steps, order):
+    """Every inter-block ZZ bond as a rank-2 operator, bonds doubled and
+    truncated back: at full bond dimension the exact Trotter state."""
+    g = Grid(R, C)
+    th = 0.6
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=th, order=order, schedule=4))
+    sv = osv.StateVector(g, th, J, H, DT, order)
+    for _ in range(steps):
+        sim.step(1)
+        sv.step()
+        a, b = sim.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"]) < 1e-11
+    psi = sim.to_statevector()
+    assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < TOL
+
+
+@pytest.mark.parametrize("R,C,chi,steps,seed,eig_path", [
+    (4, 4, 16, 1, 71, 0), (3, 5, 24, 1, 72, 0), (5, 6, 32, 1, 73, 0), (4, 4, 12, 2, 75, 0),
+    (6, 8, 16, 1, 76, 0), (4, 4, 16, 1, 71, 2)])
+def test_gate_by_gate_truncating_parity(R, C, chi, steps, seed, eig_path):
+    """Symmetry-free seeded start state, truncating bonds: observables, log F
+    and the fidelity of every bond truncation agree with the oracle's SVD
+    truncations (eig_path 2 forces the two-stage eigensolver)."""
+    sites, centre = workloads.random_mps(R, C, chi, seed)
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, schedule=4, eig_path=eig_path))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(Grid(R, C), chi, sites, centre, J, H, DT, schedule=4)
+    for _ in range(steps):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        print(R, C, chi, "z err", abs(a["z"] - b["z"]), "logF err",
+              abs(a["log_fidelity"] - b["log_fidelity"]))
+        assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
+        assert abs(a["norm"] - 1) < 1e-12
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert len(f_gpu) == len(f_ora)
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL
+    assert sim.bond_dims() == ora.bond_dims()
+
+
+@pytest.mark.parametrize("shape,chi,seed", [((2, 2, 3), 8, 74), ((2, 3, 3), 12, 77)])
+def test_gate_by_gate_cube_truncating_parity(shape, chi, seed):
+    from oracle.lattice import Cube
+    lx, ly, lz = shape
+    g = Cube(lx, ly, lz)
+    sites, centre = workloads.random_mps(lx, ly, chi, seed, dims=[2] * g.n)
+    sim = mpsim.Simulation(mpsim.make_config(lx, ly, chi, theta0=0.0, schedule=4, layers=lz,
+                                             periodic=False))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(g, chi, sites, centre, J, H, DT, schedule=4)
+    sim.step(1)
+    ora.step()
+    a, b = sim.measure(), ora.measure()
+    assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL
