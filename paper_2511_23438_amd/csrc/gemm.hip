@@ -578,12 +578,14 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
 // staged K-tile as in the square tile (the 64 x 32 narrow layout issues half).
 #define HM 128
 #define HN 32
+#define HMP (HM + 1)   // padded LDS rows: the k-major staging writes stay conflict-free
+#define HNP (HN + 1)
 
 template <int TB>
 __global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
   const ZGemm& g = gd.g;
-  __shared__ double As[3][BK][HM];
-  __shared__ double Bs[3][BK][HN];
+  __shared__ double As[3][BK][HMP];
+  __shared__ double Bs[3][BK][HNP];
   const int n0 = blockIdx.x * HN, m0 = blockIdx.y * HM;
   const int bz = blockIdx.z;
   const int bat = bz / gd.ksplit, ks = bz % gd.ksplit;
@@ -607,26 +609,26 @@ __global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
       t3[a][b] = (d4){0, 0, 0, 0};
     }
 
-  // A tile element u of this thread: below-diagonal tiles take 8 consecutive
-  // rows of one column (t & 15 picks the row group, t >> 4 the column); tiles
-  // wholly above the diagonal read the stored transpose, 8 consecutive k of
-  // one row (t >> 1 the row, t & 1 the k group)
+  // A tile element u of this thread, with neighbouring lanes on neighbouring
+  // addresses: tiles reaching below the diagonal read stored columns (lane ->
+  // row, t >> 7 and u -> column); tiles wholly above it read the stored
+  // transpose (lane -> k within 16, t >> 4 and u -> row)
   auto a_coords = [&](long k0, int u, long& gi, long& gk) {
     if (k0 < (long)m0 + HM) {
-      gk = k0 + (t >> 4);
-      gi = m0 + (t & 15) * 8 + u;
+      gi = m0 + (t & 127);
+      gk = k0 + (t >> 7) + 2 * u;
     } else {
-      gi = m0 + (t >> 1);
-      gk = k0 + (t & 1) * 8 + u;
+      gk = k0 + (t & 15);
+      gi = m0 + (t >> 4) + 16 * u;
     }
   };
   auto b_coords = [&](long k0, int u, long& gk, long& gj) {
     if (TB == 0) {
-      gk = k0 + (t >> 4);
-      gj = n0 + (t & 15) * 2 + u;
+      gj = n0 + (t & 31);
+      gk = k0 + (t >> 5) + 8 * u;
     } else {
-      gj = n0 + (t >> 3);
-      gk = k0 + (t & 7) * 2 + u;
+      gk = k0 + (t & 15);
+      gj = n0 + (t >> 4) + 16 * u;
     }
   };
   auto load = [&](long k0, cplx ra[8], cplx rb[2]) {
@@ -671,16 +673,16 @@ __global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int ii = lower ? (t & 15) * 8 + u : (t >> 1);
-      const int kk = lower ? (t >> 4) : (t & 1) * 8 + u;
+      const int ii = lower ? (t & 127) : (t >> 4) + 16 * u;
+      const int kk = lower ? (t >> 7) + 2 * u : (t & 15);
       As[0][kk][ii] = ra[u].x;
       As[1][kk][ii] = ra[u].y;
       As[2][kk][ii] = ra[u].x + ra[u].y;
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int jj = TB == 0 ? (t & 15) * 2 + u : (t >> 3);
-      const int kk = TB == 0 ? (t >> 4) : (t & 7) * 2 + u;
+      const int jj = TB == 0 ? (t & 31) : (t >> 4) + 16 * u;
+      const int kk = TB == 0 ? (t >> 5) + 8 * u : (t & 15);
       const double re = rb[u].x, im = sgb * rb[u].y;
       Bs[0][kk][jj] = re;
       Bs[1][kk][jj] = im;
