@@ -64,6 +64,10 @@ class BlockMPS:
             self._pair_cache[key] = pair_phase(self.grid, a, b, self.J, self.dt)
         return self._pair_cache[key]
 
+    def _gate_theta(self, theta: np.ndarray, i: int, gate: int) -> np.ndarray:
+        """The block-pair ZZ phase D_ab[s_a, s_b] on theta[a, s_a, s_b, c]."""
+        return theta * self._pair(self.pos[i], self.pos[i + 1])[None, :, :, None]
+
     def _single_site_gate(self, block: int, variant: int) -> np.ndarray:
         w = self.grid.block_width(block)
         dintra = np.diag(intra_phase(self.grid, block, self.J, self.dt))
@@ -103,7 +107,7 @@ class BlockMPS:
         A, B = self.sites[i], self.sites[i + 1]
         theta = np.einsum('asb,btc->astc', A, B)
         if gate:
-            theta = theta * self._pair(self.pos[i], self.pos[i + 1])[None, :, :, None]
+            theta = self._gate_theta(theta, i, gate)
         if swap:
             theta = theta.transpose(0, 2, 1, 3)
         b, d1, d2, c = theta.shape
