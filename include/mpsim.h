@@ -99,19 +99,31 @@ typedef struct {
   int32_t layers;          /* 0 or 1: the rows x cols grid above, half-row blocks. >= 2: the
                               rows x cols x layers cubic lattice with one qubit per site
                               (d = 2, snake through the cube; schedule must be 3 or 4) */
-  int32_t reserved;        /* must be 0 */
+  int32_t model;           /* 0: the transverse-field Ising model above. 1: the XY model of the
+                              supplement's section "XY Model": H = (J/2) sum (XX + YY) on the
+                              rows x cols grid with open boundaries (periodic must be 0,
+                              layers 0), one qubit per site on a row snake, trotter_order 2
+                              (the depth-7 split A/2 B/2 C/2 D C/2 B/2 A/2 of eq.
+                              "xy_trotter_step"), schedule 3 (each bond routed and returned),
+                              h ignored; the start state is eq. "xy_init" with tau = theta0:
+                              the Neel state, round(J tau / 0.02 pi) (at least one when
+                              tau > 0) Trotter steps of size tau / count, then
+                              exp(-i pi/8 H_Z); their truncations count in F_MPS */
 } mps_config;
 
 typedef struct {
   int32_t step;            /* Trotter steps applied since init */
   int32_t reserved;
-  double z;                /* <Z_tot>_MPS, eq. "Z_tot" on the normalised MPS */
-  double z2;               /* <Z_tot^2>_MPS, eq. "z2_tot" */
+  double z;                /* <Z_tot>_MPS, eq. "Z_tot" on the normalised MPS (XY model: the
+                              conserved charge density <sum_j Z_j> / n) */
+  double z2;               /* <Z_tot^2>_MPS, eq. "z2_tot" (XY model: the signal X2_tot of
+                              eq. "xy_signal", staggered by the checkerboard sign) */
   double norm;             /* <psi|psi> of the stored MPS (1 up to rounding) */
   double fidelity;         /* F_MPS = product of all truncation fidelities */
   double log_fidelity;     /* log F_MPS (accumulated on the device in float64) */
   double z_rescaled;       /* F_MPS * <Z_tot>_MPS, eq. "Z_tot_via_F" */
-  double z2_rescaled;      /* F_MPS^gamma * <Z_tot^2>_MPS, eq. "z2_tot_rescaled"; NaN if gamma < 0 */
+  double z2_rescaled;      /* F_MPS^gamma * z2, eq. "z2_tot_rescaled" (XY: the rescaled
+                              signal); NaN if gamma < 0 */
   double gamma;            /* the gamma used */
   double min_gap;          /* smallest relative gap (s_{q-1}-s_q)/s_0 at any truncation so far */
 } mps_obs;

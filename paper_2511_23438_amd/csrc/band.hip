@@ -433,29 +433,48 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
       if (it == 0) yv[l] = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)l), 0.0);
       else yv[l] = X[(long)l * ldx + kq];
     }
+    // rows entering the window in chunk kc (rows kc+WR .. kc+WR+CH-1): loaded
+    // into registers one chunk ahead, so the loads are in flight while the
+    // previous chunk's rows are eliminated; the shift by lambda is applied
+    // when they are written to LDS
+    constexpr int NPF = (CH * ABW + 63) / 64;
+    cplx pf[NPF], pfy = make_double2(0.0, 0.0);
+    auto fetch = [&](int kc) {
+#pragma unroll
+      for (int j = 0; j < NPF; ++j) {
+        const int e = l + 64 * j;
+        const long i = (long)kc + WR + e / ABW;
+        pf[j] = make_double2(0.0, 0.0);
+        if (e < CH * ABW && i < n) pf[j] = Br[i * ABW + e % ABW];
+      }
+      pfy = make_double2(0.0, 0.0);
+      if (l < CH) {
+        const long i = (long)kc + WR + l;
+        if (i < n) {
+          if (it == 0) pfy = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)i), 0.0);
+          else pfy = X[i * ldx + kq];
+        }
+      }
+    };
+    auto stage_fetched = [&](int kc) {
+#pragma unroll
+      for (int j = 0; j < NPF; ++j) {
+        const int e = l + 64 * j;
+        if (e < CH * ABW) {
+          cplx b = pf[j];
+          if (e % ABW == HB && (long)kc + WR + e / ABW < n) b.x -= lmb;
+          stage[e / ABW][e % ABW] = b;
+        }
+      }
+      if (l < CH) stage[l][ABW] = pfy;
+    };
+    fetch(0);
+    __syncthreads();
+    stage_fetched(0);
     __syncthreads();
     for (int k0 = 0; k0 < n; k0 += CH) {
-      // stage the rows entering the window in this chunk: k0+WR .. k0+WR+CH-1
-      for (int e = l; e < CH * ABW; e += 64) {
-        const int rr = e / ABW, o = e % ABW;
-        const long i = (long)k0 + WR + rr;
-        cplx b = make_double2(0.0, 0.0);
-        if (i < n) {
-          b = Br[i * ABW + o];
-          if (o == HB) b.x -= lmb;
-        }
-        stage[rr][o] = b;
-      }
-      if (l < CH) {
-        const long i = (long)k0 + WR + l;
-        cplx y0 = make_double2(0.0, 0.0);
-        if (i < n) {
-          if (it == 0) y0 = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)i), 0.0);
-          else y0 = X[i * ldx + kq];
-        }
-        stage[l][ABW] = y0;
-      }
-      __syncthreads();
+      const bool more = k0 + CH < n;
+      if (more) fetch(k0 + CH);
       const int kend = min(n, k0 + CH);
       for (int k = k0; k < kend; ++k) {
         const int cs = k % WC;
@@ -548,18 +567,40 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
         }
         __syncthreads();
       }
+      if (more) {
+        stage_fetched(k0 + CH);
+        __syncthreads();
+      }
     }
     // ---- back substitution: lane l holds x[jc] for the jc = l (mod 64) in
     // [k+1, k+64]; rows staged CH at a time from U
     cplx xr = make_double2(0.0, 0.0);
     double mx = 0.0;
+    // U rows of the next chunk are loaded one chunk ahead, like the forward rows
+    constexpr int NPB = (CH * URW + 63) / 64;
+    cplx pb[NPB];
+    auto fetch_u = [&](int kb) {
+      const int klo = max(0, kb - CH + 1);
+      const int cnt = (kb - klo + 1) * URW;
+#pragma unroll
+      for (int j = 0; j < NPB; ++j) {
+        const int e = l + 64 * j;
+        pb[j] = (e < cnt) ? U[(long)klo * URW + e] : make_double2(0.0, 0.0);
+      }
+    };
+    fetch_u(n - 1);
     for (int kb = n - 1; kb >= 0; kb -= CH) {
       const int klo = max(0, kb - CH + 1);
-      for (int e = l; e < (kb - klo + 1) * URW; e += 64) {
-        const int rr = e / URW, o = e % URW;
-        stage[rr][o] = U[(long)(klo + rr) * URW + o];
+      {
+        const int cnt = (kb - klo + 1) * URW;
+#pragma unroll
+        for (int j = 0; j < NPB; ++j) {
+          const int e = l + 64 * j;
+          if (e < cnt) stage[e / URW][e % URW] = pb[j];
+        }
       }
       __syncthreads();
+      if (kb - CH >= 0) fetch_u(kb - CH);
       for (int k = kb; k >= klo; --k) {
         const int rr = k - klo;
         const int o = ((l - (k + 1)) % 64 + 64) % 64 + 1;   // jc = k + o

@@ -1106,8 +1106,11 @@ __device__ inline cplx qr_butterfly(cplx vals[QR_NB], int lane, int& vid) {
 
 // partial sums of the first column c of a panel (rows c+1 .. m-1)
 __global__ __launch_bounds__(256) void k_qr_first(int m, const cplx* A, long rs, long cs, int c,
-                                                  int pe, cplx* part) {
+                                                  int pe, cplx* piv, cplx* part) {
   const int t = threadIdx.x, lane = t & 63;
+  // copy of the pivot row c (columns c .. pe-1) for the first column step
+  if (blockIdx.x == 0 && t < QR_NB)
+    piv[t] = (c + t < pe) ? A[(long)c * rs + (long)(c + t) * cs] : make_double2(0.0, 0.0);
   const long r = c + 1 + (long)blockIdx.x * 256 + t;
   const bool in = r < m;
   const cplx x = in ? A[r * rs + (long)c * cs] : make_double2(0.0, 0.0);
@@ -1123,24 +1126,50 @@ __global__ __launch_bounds__(256) void k_qr_first(int m, const cplx* A, long rs,
   if ((lane & 1) == 0) part[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + vid] = z;
 }
 
+// The pivot row c is read from piv, a copy written by the previous launch:
+// workgroup 0 rewrites row c of A during this launch, so no other workgroup
+// may read it there. The thread holding row c + 1 writes its updated values
+// to piv_next for the next launch.
 __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs, int c, int pe,
-                                                const cplx* part, int nparts, cplx* part_next,
-                                                cplx* tau_out) {
+                                                const cplx* piv, const cplx* part, int nparts,
+                                                cplx* piv_next, cplx* part_next, cplx* tau_out) {
   __shared__ cplx red[8][QR_NB];
+  __shared__ cplx prow[QR_NB];
   __shared__ cplx wj[QR_NB];
   __shared__ double sh[5];
   const int t = threadIdx.x, lane = t & 63;
   const int ncol = pe - c - 1;  // later columns of the panel
+  // every global value the step needs is requested first, so the loads of
+  // the pivot row and of this thread's row overlap the reduction
+  const long r = c + (long)blockIdx.x * 256 + t;
+  const bool in = r < m;
+  cplx a[QR_NB];  // this thread's row, columns c .. c + QR_NB - 1
+#pragma unroll
+  for (int u = 0; u < QR_NB; ++u)
+    a[u] = (in && c + u < pe) ? A[r * rs + (long)(c + u) * cs] : make_double2(0.0, 0.0);
+  cplx pr = make_double2(0.0, 0.0);
+  if (t < QR_NB) pr = piv[t];
   {
-    // reduce the partials: thread (g, u) sums parts g, g + 8, ...
+    // reduce the partials: thread (g, u) sums parts g, g + 8, ... with 16
+    // loads in flight per round (the partials come from every XCD, so the
+    // reduction is bound by load latency; summation order as a plain loop)
     const int u = t & (QR_NB - 1), g = t >> 5;
     cplx acc = make_double2(0.0, 0.0);
     if (u < ncol || u == QR_NB - 1) {
-#pragma unroll 4
-      for (int p = g; p < nparts; p += 8) acc = cadd(acc, part[(long)p * QR_NB + u]);
+      for (int p0 = g; p0 < nparts; p0 += 8 * 16) {
+        cplx pv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int p = p0 + 8 * i;
+          pv[i] = (p < nparts) ? part[(long)p * QR_NB + u] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc = cadd(acc, pv[i]);
+      }
     }
     red[g][u] = acc;
   }
+  if (t < QR_NB) prow[t] = pr;
   __syncthreads();
   if (t < QR_NB) {
     cplx sum = red[0][t];
@@ -1151,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs
   if (t == 0) {
     double beta;
     cplx tau, scl;
-    reflector(A[(long)c * rs + (long)c * cs], red[0][QR_NB - 1].x, beta, tau, scl);
+    reflector(prow[0], red[0][QR_NB - 1].x, beta, tau, scl);
     sh[0] = beta; sh[1] = tau.x; sh[2] = tau.y; sh[3] = scl.x; sh[4] = scl.y;
     if (blockIdx.x == 0) tau_out[c] = tau;
   }
@@ -1159,15 +1188,12 @@ __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs
   const cplx sc = make_double2(sh[3], sh[4]);
   const cplx tau = make_double2(sh[1], sh[2]);
   if (t < ncol)  // v^H A[:, jj] = A[c, jj] + conj(scale) * sum_r conj(A[r,c]) A[r,jj]
-    wj[t] = cadd(A[(long)c * rs + (long)(c + 1 + t) * cs], cmulc(sc, red[0][t]));
+    wj[t] = cadd(prow[t + 1], cmulc(sc, red[0][t]));
   __syncthreads();
-  const long r = c + (long)blockIdx.x * 256 + t;
-  const bool in = r < m;
-  cplx a[QR_NB - 1];
   const cplx ctau = cconj(tau);
   cplx v = make_double2(0.0, 0.0);
   if (in) {
-    v = (r == c) ? make_double2(1.0, 0.0) : cmul(A[r * rs + (long)c * cs], sc);
+    v = (r == c) ? make_double2(1.0, 0.0) : cmul(a[0], sc);
     A[r * rs + (long)c * cs] = (r == c) ? make_double2(sh[0], 0.0) : v;
   }
 #pragma unroll
@@ -1175,12 +1201,16 @@ __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs
     const int jj = c + 1 + u;
     cplx val = make_double2(0.0, 0.0);
     if (in && jj < pe) {
-      val = csub(A[r * rs + (long)jj * cs], cmul(ctau, cmul(v, wj[u])));
+      val = csub(a[u + 1], cmul(ctau, cmul(v, wj[u])));
       A[r * rs + (long)jj * cs] = val;
     }
     a[u] = val;
   }
   if (c + 1 >= pe) return;
+  if (r == c + 1) {
+#pragma unroll
+    for (int u = 0; u < QR_NB; ++u) piv_next[u] = (u < QR_NB - 1) ? a[u] : make_double2(0.0, 0.0);
+  }
   // partial sums of column c + 1 over rows c+2 .. m-1
   const bool act = in && r >= c + 2;
   const cplx x = act ? a[0] : make_double2(0.0, 0.0);
@@ -1196,18 +1226,23 @@ __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs
 
 void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream_t s) {
   const int kmin = std::min(m, k);
-  // two partial-sum buffers, alternating between column steps
-  cplx* partA = w.tpart;
-  cplx* partB = w.tpart + w.tpart_elems / 2;
+  // two buffers of (pivot row copy, partial sums), alternating between
+  // column steps
+  cplx* pivA = w.tpart;
+  cplx* pivB = w.tpart + w.tpart_elems / 2;
+  cplx* partA = pivA + QR_NB;
+  cplx* partB = pivB + QR_NB;
   for (int p0 = 0, panel = 0; p0 < kmin; p0 += QR_NB, ++panel) {
     const int pe = std::min(p0 + QR_NB, kmin);
     const int nb0 = std::max(1, ceil_div(m - p0 - 1, 256));
-    hipLaunchKernelGGL(k_qr_first, dim3(nb0), dim3(256), 0, s, m, (const cplx*)A, rs, cs, p0, pe, partA);
+    hipLaunchKernelGGL(k_qr_first, dim3(nb0), dim3(256), 0, s, m, (const cplx*)A, rs, cs, p0, pe, pivA,
+                       partA);
     int nparts = nb0 * 4;
     for (int c = p0; c < pe; ++c) {
       const int nbr = ceil_div(m - c, 256);
-      hipLaunchKernelGGL(k_qr_col, dim3(nbr), dim3(256), 0, s, m, A, rs, cs, c, pe,
-                         (const cplx*)partA, nparts, partB, w.qtau);
+      hipLaunchKernelGGL(k_qr_col, dim3(nbr), dim3(256), 0, s, m, A, rs, cs, c, pe, (const cplx*)pivA,
+                         (const cplx*)partA, nparts, pivB, partB, w.qtau);
+      std::swap(pivA, pivB);
       std::swap(partA, partB);
       nparts = nbr * 4;
     }

@@ -11,6 +11,11 @@ void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream
 // doubled bonds take index 2 * old + k
 void launch_mpo_site(const cplx* src, cplx* dst, int b0, int d, int b1, int mode, int w, int bit,
                      double c, double sn, hipStream_t s);
+// dense two-qubit gate G (4 x 4) on theta of two d = 2 sites, in place,
+// SWAP of the physical indices folded into the store when swap is set
+void launch_theta_gate4(cplx* theta, int b0, int b2, const cplx* G, int swap, hipStream_t s);
+// measurement with sign * X on a d = 2 site (see launch_meas_combine)
+void launch_meas_combine_x(cplx* X, int b, int b2, double sign, hipStream_t s);
 // dst[slot] = sum |x|^2 over len entries (deterministic two-pass reduction).
 void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStream_t s);
 // Truncation bookkeeping: f = sc[3]/sc[2], sc[0] += log f, sc[4] = 1/sqrt(sc[3]),

@@ -68,6 +68,71 @@ void launch_mpo_site(const cplx* src, cplx* dst, int b0, int d, int b1, int mode
                      w, bit, c, sn);
 }
 
+// Dense two-qubit gate on theta of two d = 2 sites, (2 b0) x (2 b2)
+// row-major: for every (a, c) the four values theta[a, s1, s2, c] are mixed
+// by G (row-major 4 x 4 over s1 s2, s1 the more significant) and written
+// back, at [a, t2, t1, c] when swap is set. Each thread owns one (a, c), so
+// the update is in place.
+__global__ void k_theta_gate4(cplx* th, int b0, int b2, const cplx* G, int swap) {
+  __shared__ cplx Gs[16];
+  if (threadIdx.x < 16) Gs[threadIdx.x] = G[threadIdx.x];
+  __syncthreads();
+  const long pairs = (long)b0 * b2;
+  const long ld = 2L * b2;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < pairs;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long a = idx / b2, c = idx % b2;
+    cplx v[4];
+#pragma unroll
+    for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) v[s1 * 2 + s2] = th[(a * 2 + s1) * ld + s2 * b2 + c];
+#pragma unroll
+    for (int t1 = 0; t1 < 2; ++t1)
+#pragma unroll
+      for (int t2 = 0; t2 < 2; ++t2) {
+        cplx acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = cadd(acc, cmul(Gs[(t1 * 2 + t2) * 4 + u], v[u]));
+        const long at = swap ? (a * 2 + t2) * ld + t1 * b2 + c : (a * 2 + t1) * ld + t2 * b2 + c;
+        th[at] = acc;
+      }
+  }
+}
+
+void launch_theta_gate4(cplx* theta, int b0, int b2, const cplx* G, int swap, hipStream_t s) {
+  const long pairs = (long)b0 * b2;
+  const int blocks = (int)std::min<long>((pairs + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_theta_gate4, dim3(std::max(blocks, 1)), dim3(256), 0, s, theta, b0, b2, G, swap);
+}
+
+// Measurement with the operator sign * X on a d = 2 site: X holds the three
+// stacked blocks X0, X1, X2 (each b x (2 b2)); Y1 = X1 + sign X X0,
+// Y2 = X2 + 2 sign X X1 + X0 (X^2 = I), X flipping the physical index.
+// Each thread owns one (a, c) and both physical values.
+__global__ void k_meas_combine_x(cplx* X, int b, int b2, double sign) {
+  const long blk = 2L * b * b2;
+  const long pairs = (long)b * b2;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < pairs;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long a = idx / b2, c = idx % b2;
+    const long i0 = (a * 2) * b2 + c, i1 = (a * 2 + 1) * b2 + c;
+    const cplx x00 = X[i0], x01 = X[i1];
+    const cplx x10 = X[blk + i0], x11 = X[blk + i1];
+    const cplx x20 = X[2 * blk + i0], x21 = X[2 * blk + i1];
+    X[blk + i0] = cadd(x10, cscale(x01, sign));
+    X[blk + i1] = cadd(x11, cscale(x00, sign));
+    X[2 * blk + i0] = cadd(cadd(x20, cscale(x11, 2.0 * sign)), x00);
+    X[2 * blk + i1] = cadd(cadd(x21, cscale(x10, 2.0 * sign)), x01);
+  }
+}
+
+void launch_meas_combine_x(cplx* X, int b, int b2, double sign, hipStream_t s) {
+  const long pairs = (long)b * b2;
+  const int blocks = (int)std::min<long>((pairs + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_meas_combine_x, dim3(std::max(blocks, 1)), dim3(256), 0, s, X, b, b2, sign);
+}
+
 void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream_t s) {
   long pairs = (long)b0 * b1;
   int blocks = (int)std::min<long>((pairs + 255) / 256, 4096);

@@ -60,7 +60,8 @@ struct mps_sim {
   cplx* d_pairs = nullptr;
   std::vector<long> pair_off;
   cplx* d_gates = nullptr;
-  std::vector<long> gate_off[3];
+  std::vector<long> gate_off[4];
+  cplx* d_xy = nullptr;  // XY model: gates 1..4, 16 complex each
   double* d_zsum = nullptr;
   std::vector<long> zsum_off;
 
@@ -177,7 +178,8 @@ LwSizes lw_sizes(const Sizes& z) {
   LwSizes l;
   l.W = z.nmax * TRD_NB;
   long nparts = (long)ceil_div(z.mmax, 256) * 4;
-  l.tpart = std::max(nparts * (2 * TRD_NB + 1), nparts * QR_NB);
+  // QR column steps: two halves of (pivot row copy, nparts x QR_NB partials)
+  l.tpart = std::max(nparts * (2 * TRD_NB + 1), 2 * (QR_NB + nparts * QR_NB));
   long nt = ceil_div(z.nmax, 64);
   l.P = nt * nt * 64;
   l.dpart = std::max(nparts, nt + 1);
@@ -330,7 +332,9 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   g.phase = nullptr;
   g.tag = PROF_THETA;
   g.prec = h->gprec;
-  if (gate) {
+  const bool dense_gate = p.model == 1 && gate;
+  if (dense_gate) g.swap = 0;  // the dense gate kernel applies the SWAP
+  if (gate && p.model == 0) {
     int pi = p.coupled(ba, bb);
     if (pi >= 0) {
       g.phase = h->d_pairs + h->pair_off[pi];
@@ -338,6 +342,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     }
   }
   zgemm(g, nullptr, 0, s, &h->prof);
+  if (dense_gate) launch_theta_gate4(h->theta, b0, b2, h->d_xy + 16 * gate, swap, s);
   norm2(h, h->theta, mo * no, 2);
 
   bool left;
@@ -531,7 +536,25 @@ mps_status check_device(mps_sim* h) {
 }
 
 // Measurement sweep: three left environments for 1, Z_tot and Z_tot^2.
-void measure_sweep(mps_sim* h, double out[3]) {
+// XY model preparation (eq. "xy_init"): the Trotter steps of size dtau from
+// the Neel state, then exp(-i pi/8 H_Z) on every site.
+void xy_prepare(mps_sim* h) {
+  const Plan& p = h->plan;
+  for (int k = 0; k < p.nprep; ++k) {
+    std::vector<Op> ops;
+    p.xy_ops(h->pos, ops, true);
+    for (size_t i = 0; i < ops.size(); ++i) {
+      int next = -1;
+      for (size_t i2 = i + 1; i2 < ops.size(); ++i2) { next = ops[i2].site; break; }
+      two_site(h, ops[i].site, ops[i].swap, ops[i].gate, next);
+    }
+  }
+  for (int st = 0; st < p.N; ++st) single_site(h, st, 3);
+}
+
+// op 0: Z_tot moments (diagonal z sums); op 1: staggered X (XY model)
+void measure_sweep(mps_sim* h, double out[3], int op = 0);
+void measure_sweep(mps_sim* h, double out[3], int op) {
   const Plan& p = h->plan;
   hipStream_t s = h->stream;
   launch_env_init(h->env[0], s);
@@ -549,7 +572,8 @@ void measure_sweep(mps_sim* h, double out[3]) {
     g1.B.stride = 0;
     g1.strideC = xs;
     zgemm(g1, nullptr, 0, s, &h->prof);
-    launch_meas_combine(h->envx, b, d, b2, h->d_zsum + h->zsum_off[blk], s);
+    if (op == 1) launch_meas_combine_x(h->envx, b, b2, (double)p.stagger[blk], s);
+    else launch_meas_combine(h->envx, b, d, b2, h->d_zsum + h->zsum_off[blk], s);
     // E'_k = A^H Y_k
     ZGemm g2 = zgemm_args(b2, b2, b * d, zop(h->site[st], b2, 1, 1), zop(h->envx, b2, 0), h->env[1 - cur], b2,
                           0, one, zero);
@@ -577,6 +601,12 @@ void upload_product_state(mps_sim* h) {
       double amp = 1.0;
       for (int j = 0; j < w; ++j) amp *= (((idx >> (w - 1 - j)) & 1) == 0) ? c : sn;
       v[idx] = make_double2(amp, 0.0);
+    }
+    if (p.model == 1) {
+      // Neel state, the ground state of H_Z = sum_j (-1)^j Z_j: |1> where the
+      // checkerboard sign is +1, |0> where it is -1
+      v[0] = make_double2(p.stagger[blk] == 1 ? 0.0 : 1.0, 0.0);
+      v[1] = make_double2(p.stagger[blk] == 1 ? 1.0 : 0.0, 0.0);
     }
     HIPCHK(copy_sync(h, h->site[st], v.data(), sizeof(cplx) * d, hipMemcpyHostToDevice));
   }
@@ -725,7 +755,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     }
     long goff = 0;
     std::vector<cplx> hg;
-    for (int v = 0; v < 3; ++v)
+    for (int v = 0; v < 4; ++v)
       for (int b = 0; b < p.nblocks(); ++b) {
         h->gate_off[v].push_back(goff);
         for (auto& z2 : p.site_gate[v][b]) hg.push_back(make_double2(z2.real(), z2.imag()));
@@ -740,6 +770,13 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     }
     h->d_zsum = dalloc<double>(h, (long)hz.size());
     HIPCHK(copy_sync(h, h->d_zsum, hz.data(), sizeof(double) * hz.size(), hipMemcpyHostToDevice));
+    if (p.model == 1) {
+      std::vector<cplx> hx(5 * 16, make_double2(0.0, 0.0));
+      for (int v = 1; v <= 4; ++v)
+        for (int k = 0; k < 16; ++k) hx[v * 16 + k] = make_double2(p.xy_gate[v][k].real(), p.xy_gate[v][k].imag());
+      h->d_xy = dalloc<cplx>(h, 5 * 16);
+      HIPCHK(copy_sync(h, h->d_xy, hx.data(), sizeof(cplx) * hx.size(), hipMemcpyHostToDevice));
+    }
     // state
     h->pos = p.snake();
     h->bond.assign(p.N + 1, 1);
@@ -748,6 +785,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->log_cap = 0;
     ensure_log(h, 64L * (11 * p.R + 4));
     reset_bookkeeping(h);
+    if (p.model == 1) xy_prepare(h);
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (NoMem&) {
     mps_free(h);
@@ -823,9 +861,11 @@ mps_status mps_sync(mps_handle h) {
 mps_status mps_measure(mps_handle h, double gamma, mps_obs* out) {
   GUARD(h);
   if (!out) return fail(h, MPS_E_INVAL, "out is NULL");
-  double e[3];
+  double e[3], ex[3] = {0.0, 0.0, 0.0};
   double sc[2];
-  TRYDEV(h, measure_sweep(h, e);
+  const bool xy = h->plan.model == 1;
+  TRYDEV(h, measure_sweep(h, e, 0);
+         if (xy) measure_sweep(h, ex, 1);
          HIPCHK(copy_sync(h, sc, h->dscal, sizeof(sc), hipMemcpyDeviceToHost)));
   mps_status st = check_device(h);
   if (st != MPS_OK) return st;
@@ -834,7 +874,7 @@ mps_status mps_measure(mps_handle h, double gamma, mps_obs* out) {
   o.step = h->steps;
   o.norm = e[0];
   o.z = e[1] / (n * e[0]);
-  o.z2 = e[2] / (n * n * e[0]);
+  o.z2 = xy ? ex[2] / (n * n * ex[0]) : e[2] / (n * n * e[0]);
   if (!std::isfinite(o.z) || !std::isfinite(o.z2)) return fail(h, MPS_E_NUMERIC, "non-finite observable");
   o.log_fidelity = sc[0];
   o.fidelity = std::exp(sc[0]);

@@ -17,9 +17,16 @@ namespace mpsim {
 
 mps_status validate(const mps_config* cfg, const char** msg) {
   if (!cfg) { *msg = "config is NULL"; return MPS_E_INVAL; }
-  if (cfg->reserved != 0) { *msg = "reserved must be 0"; return MPS_E_INVAL; }
   if (cfg->layers < 0) { *msg = "layers must be >= 0"; return MPS_E_INVAL; }
-  if (cfg->layers >= 2) {
+  if (cfg->model != 0 && cfg->model != 1) { *msg = "model must be 0 (TFIM) or 1 (XY)"; return MPS_E_INVAL; }
+  if (cfg->model == 1) {
+    if (cfg->layers != 0) { *msg = "the XY model runs on the grid (layers 0)"; return MPS_E_INVAL; }
+    if (cfg->periodic != 0) { *msg = "the XY model has open boundaries (periodic 0)"; return MPS_E_INVAL; }
+    if (cfg->trotter_order != 2) { *msg = "the XY step is second order (trotter_order 2)"; return MPS_E_INVAL; }
+    if (cfg->schedule != 3) { *msg = "the XY model uses schedule 3"; return MPS_E_INVAL; }
+    if (cfg->rows < 1 || cfg->cols < 1 || cfg->rows * cfg->cols < 2) { *msg = "need at least 2 qubits"; return MPS_E_INVAL; }
+    if ((long)cfg->rows * cfg->cols > 256) { *msg = "XY grid with > 256 qubits unsupported"; return MPS_E_UNSUPPORTED; }
+  } else if (cfg->layers >= 2) {
     if (cfg->rows < 1 || cfg->cols < 1) { *msg = "cube extents must be >= 1"; return MPS_E_INVAL; }
     if ((long)cfg->rows * cfg->cols * cfg->layers > 256) { *msg = "cube with > 256 sites unsupported"; return MPS_E_UNSUPPORTED; }
     if (cfg->schedule != 3 && cfg->schedule != 4) { *msg = "the cube needs schedule 3 or 4"; return MPS_E_INVAL; }
@@ -43,7 +50,44 @@ mps_status validate(const mps_config* cfg, const char** msg) {
 
 std::vector<int> Plan::snake() const { return snake_order; }
 
+// XY model, one step (supplement, eq. "xy_trotter_step"): sublayers
+// A/2 B/2 C/2 D C/2 B/2 A/2; inside a sublayer the bonds are taken in the
+// order of their chain positions, and each is routed and returned: the qubit
+// at pb is swapped leftwards to pa+1, the gate acts on (pa, pa+1), and it is
+// swapped back.
+void Plan::xy_ops(std::vector<int>& pos, std::vector<Op>& out, bool prep) const {
+  static const int layer[7] = {0, 1, 2, 3, 2, 1, 0};
+  static const int variant[7] = {1, 1, 1, 2, 1, 1, 1};
+  auto u2 = [&](int site, int swap, int gate) {
+    Op o{};
+    o.kind = 1; o.site = site; o.swap = swap; o.gate = gate;
+    o.block_a = pos[site]; o.block_b = pos[site + 1];
+    out.push_back(o);
+    if (swap) std::swap(pos[site], pos[site + 1]);
+  };
+  for (int k = 0; k < 7; ++k) {
+    std::vector<int> where(nb, 0);
+    for (int p = 0; p < N; ++p) where[pos[p]] = p;
+    std::vector<std::pair<int, int>> pairs;
+    for (auto& bd : xy_sub[layer[k]])
+      pairs.push_back({std::min(where[bd.first], where[bd.second]),
+                       std::max(where[bd.first], where[bd.second])});
+    std::sort(pairs.begin(), pairs.end());
+    const int gv = variant[k] + (prep ? 2 : 0);
+    for (auto& pr : pairs) {
+      const int pa = pr.first, pb = pr.second;
+      for (int p = pb - 1; p > pa; --p) u2(p, 1, 0);
+      u2(pa, 0, gv);
+      for (int p = pa + 1; p < pb; ++p) u2(p, 1, 0);
+    }
+  }
+}
+
 void Plan::step_ops(std::vector<int>& pos, std::vector<Op>& out) const {
+  if (model == 1) {
+    xy_ops(pos, out, false);
+    return;
+  }
   auto u2 = [&](int site, int swap, int gate) {
     Op o{};
     o.kind = 1; o.site = site; o.swap = swap;
@@ -186,6 +230,33 @@ static void cube_geometry(const mps_config* cfg, Plan& p) {
         }
 }
 
+// XY model: one qubit per site on the rows x cols grid, row snake (even rows
+// left to right, odd rows right to left), open boundaries; sublayers A / B:
+// horizontal bonds whose first column is even / odd, C / D: vertical bonds
+// whose first row is even / odd.
+static void xy_geometry(const mps_config* cfg, Plan& p) {
+  const int R = cfg->rows, C = cfg->cols;
+  p.R = R; p.C = C; p.Lz = 0;
+  p.n = R * C; p.N = p.n; p.nb = p.n;
+  p.wL = p.wR = 1;
+  p.dmax = 2;
+  p.block_width.assign(p.nb, 1);
+  p.block_qubits.assign(p.nb, {});
+  for (int q = 0; q < p.n; ++q) p.block_qubits[q].push_back(q);
+  p.snake_order.clear();
+  for (int r = 0; r < R; ++r)
+    for (int cc = 0; cc < C; ++cc) p.snake_order.push_back(r * C + ((r % 2 == 0) ? cc : C - 1 - cc));
+  p.xy_sub.assign(4, {});
+  p.bonds.clear();
+  for (int r = 0; r < R; ++r)
+    for (int c = 0; c < C; ++c) {
+      if (c + 1 < C) p.xy_sub[c % 2].push_back({r * C + c, r * C + c + 1});
+      if (r + 1 < R) p.xy_sub[2 + r % 2].push_back({r * C + c, (r + 1) * C + c});
+    }
+  p.stagger.assign(p.n, 1);
+  for (int q = 0; q < p.n; ++q) p.stagger[q] = ((q / C + q % C) % 2 == 0) ? 1 : -1;
+}
+
 // Grid: half-row blocks (ceil(C/2) and floor(C/2) columns), row snake of
 // blocks, right and down neighbours with wrap.
 static void grid_geometry(const mps_config* cfg, Plan& p) {
@@ -232,7 +303,9 @@ void build_plan(const mps_config* cfg, Plan& p) {
   p.schedule = cfg->schedule;
   p.eig_path = cfg->eig_path;
   p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
-  if (cfg->layers >= 2) cube_geometry(cfg, p);
+  p.model = cfg->model;
+  if (cfg->model == 1) xy_geometry(cfg, p);
+  else if (cfg->layers >= 2) cube_geometry(cfg, p);
   else grid_geometry(cfg, p);
   const int nb = p.nb;
   std::vector<int> blk_of(p.n), idx_in(p.n);
@@ -272,7 +345,7 @@ void build_plan(const mps_config* cfg, Plan& p) {
     p.pair_phase.push_back(ph);
   }
   // single-site gates
-  for (int v = 0; v < 3; ++v) p.site_gate[v].assign(nb, {});
+  for (int v = 0; v < 4; ++v) p.site_gate[v].assign(nb, {});
   p.zsum.assign(nb, {});
   for (int b = 0; b < nb; ++b) {
     int w = p.block_width[b], d = p.dim(b);
@@ -302,6 +375,14 @@ void build_plan(const mps_config* cfg, Plan& p) {
         p.site_gate[0][b][i * d + j] = full[i * d + j] * dintra[j];  // U_X * D_intra
         p.site_gate[1][b][i * d + j] = dintra[i] * half[i * d + j];  // D_intra * U_X(half)
       }
+    // XY preparation's last factor exp(-i pi/8 H_Z), H_Z = sum_j (-1)^j Z_j
+    // (identity outside the XY model)
+    p.site_gate[3][b].assign(d * d, zc(0.0, 0.0));
+    for (int i = 0; i < d; ++i) {
+      double hz = 0.0;
+      if (p.model == 1) hz = p.stagger[b] * zval(i, w, 0);
+      p.site_gate[3][b][i * d + i] = std::exp(zc(0.0, -0.125 * M_PI * hz));
+    }
     p.zsum[b].resize(d);
     for (int s = 0; s < d; ++s) {
       double z = 0;
@@ -315,6 +396,27 @@ void build_plan(const mps_config* cfg, Plan& p) {
     double lim = std::min((double)p.chi, std::min(std::pow((double)p.dmax, b),
                                                    std::pow((double)p.dmax, p.N - b)));
     p.cap[b] = (int)lim;
+  }
+  // XY gates exp(-i phi (XX + YY)): XX + YY = 2 (|01><10| + |10><01|)
+  if (p.model == 1) {
+    long k = 0;
+    double dtau = 0.0;
+    if (p.theta0 != 0.0) {
+      k = std::lround(std::fabs(p.J * p.theta0) / (0.02 * M_PI));
+      if (k < 1) k = 1;
+      dtau = p.theta0 / (double)k;
+    }
+    p.nprep = (int)k;
+    p.dtau = dtau;
+    const double phis[5] = {0.0, p.J * p.dt / 4, p.J * p.dt / 2, p.J * dtau / 4, p.J * dtau / 2};
+    for (int v = 1; v <= 4; ++v) {
+      const double c = std::cos(2 * phis[v]), sn = std::sin(2 * phis[v]);
+      std::vector<zc> G(16, zc(0.0, 0.0));
+      G[0] = G[15] = 1.0;
+      G[5] = G[10] = c;
+      G[6] = G[9] = zc(0.0, -sn);
+      p.xy_gate[v] = G;
+    }
   }
   // rank bound of each bond in the start order (blocks keep their sites
   // under schedule 4): the smaller product of local dimensions on its sides

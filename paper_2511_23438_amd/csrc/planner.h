@@ -40,7 +40,17 @@ struct Plan {
   // gate tables: pair index of ordered (a, b) with a < b; -1 = not coupled
   std::vector<int> pair_index;                // [a * nblocks + b]
   std::vector<std::vector<zc>> pair_phase;    // [pair] d_a x d_b, row-major
-  std::vector<std::vector<zc>> site_gate[3];  // [variant][block] d x d
+  std::vector<std::vector<zc>> site_gate[4];  // [variant][block] d x d (3: XY staggered Z phase)
+  // XY model (model 1): sublayers A, B, C, D of bonds (qubit pairs), the
+  // dense two-qubit gates exp(-i phi (XX + YY)) (row-major 4 x 4; variant
+  // 1 / 2: half / full step dt, 3 / 4: half / full preparation step dtau),
+  // the checkerboard sign of every qubit and the preparation step count
+  int model = 0;
+  std::vector<std::vector<std::pair<int, int>>> xy_sub;
+  std::vector<zc> xy_gate[5];
+  std::vector<int> stagger;
+  int nprep = 0;
+  double dtau = 0.0;
   std::vector<std::vector<double>> zsum;      // [block] d entries
 
   int nblocks() const { return nb; }
@@ -53,6 +63,8 @@ struct Plan {
   std::vector<int> snake() const;
   // ops of one step from order `pos`; pos is updated to the end order
   void step_ops(std::vector<int>& pos, std::vector<Op>& out) const;
+  // XY model: ops of one step (prep: with the preparation step's gates)
+  void xy_ops(std::vector<int>& pos, std::vector<Op>& out, bool prep) const;
 };
 
 // Validate a config; returns MPS_OK or an error code with a message.

@@ -44,7 +44,7 @@ class MpsConfig(C.Structure):
                 ("schedule", C.c_int32), ("periodic", C.c_int32), ("eig_path", C.c_int32),
                 ("J", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("theta0", C.c_double), ("seed", C.c_uint64), ("layers", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("model", C.c_int32)]
 
 
 class MpsObs(C.Structure):
@@ -130,6 +130,15 @@ def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
                      1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0)
 
 
+def make_xy_config(rows: int, cols: int, chi: int, g: float = 1.0,
+                   dt: float = 0.05 * math.pi, tau: float = 0.06 * math.pi,
+                   precision: str = "fp64", seed: int = 0, eig_path: int = 0) -> MpsConfig:
+    """XY-model quench (model 1): rows x cols grid, open boundaries, one qubit
+    per site, coupling g, step dt, start state of preparation time tau."""
+    return MpsConfig(rows, cols, chi, PRECISION[precision], 2, 3, 0, eig_path, g, 0.0, dt,
+                     tau, seed, 0, 1)
+
+
 def config_from_instance(inst, seed: int = 0) -> MpsConfig:
     return make_config(inst.rows, inst.cols, inst.chi, inst.J, inst.h, inst.dt,
                        inst.theta0, inst.order, inst.precision, True, seed,
@@ -206,8 +215,8 @@ class Simulation:
         self.h = H()
         _check(_lib.mps_init_product(C.byref(cfg), ap, C.c_void_p(self.stream),
                                      C.byref(self.h)))
-        if cfg.layers >= 2:      # cube: one qubit per site
-            self.n = cfg.rows * cfg.cols * cfg.layers
+        if cfg.layers >= 2 or cfg.model == 1:      # cube or XY: one qubit per site
+            self.n = cfg.rows * cfg.cols * max(cfg.layers, 1)
             self.N = self.n
         else:                    # grid: two half-row blocks per row
             self.n = cfg.rows * cfg.cols

@@ -88,3 +88,32 @@ def test_footprint_monotone_and_fits():
     # sites alone: 7 bulk sites of chi*16*chi complex128
     assert fp[2] > 7 * 1024 * 16 * 1024 * 16
     assert fp[2] < 288 * 2 ** 30
+
+
+@pytest.mark.parametrize("shape", [(2, 3), (3, 3), (4, 4), (1, 5), (6, 6), (5, 4)])
+def test_xy_schedule_equals_oracle(shape):
+    """XY model: the C++ planner's sublayer / route-and-return list equals the
+    oracle's for two steps."""
+    from oracle.xy import XYGrid, xy_step_ops
+    g = XYGrid(*shape)
+    cfg = mpsim.make_xy_config(shape[0], shape[1], 16)
+    got = mpsim.schedule_dump(cfg, 2)
+    pos = g.snake()
+    ref = xy_step_ops(g, pos) + xy_step_ops(g, pos)
+    assert pos == g.snake()
+    _same_ops(got, ref)
+
+
+@pytest.mark.parametrize("field,value", [("periodic", 1), ("trotter_order", 1), ("layers", 2),
+                                         ("schedule", 1), ("model", 2)])
+def test_xy_invalid_configs(field, value):
+    cfg = mpsim.make_xy_config(3, 3, 8)
+    setattr(cfg, field, value)
+    with pytest.raises(mpsim.MpsError) as e:
+        mpsim.schedule_dump(cfg, 1)
+    assert e.value.status == mpsim.MPS_E_INVAL
+
+
+def test_xy_footprint():
+    fp = mpsim.footprint_bytes(mpsim.make_xy_config(6, 6, 256))
+    assert 0 < fp < 8 * 2 ** 30

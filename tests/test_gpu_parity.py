@@ -435,3 +435,66 @@ def test_gate_by_gate_cube_truncating_parity(shape, chi, seed):
     f_gpu, _ = sim.truncation_log()
     f_ora = np.array([u["f"] for u in ora.update_log])
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
+
+
+# ---- XY model (model 1): one qubit per site, dense U(1) pair gates ----
+
+XY_G, XY_DT = 1.0, 0.05 * math.pi
+
+
+@pytest.mark.parametrize("shape,chi,steps,tau", [((2, 3), 8, 3, 0.06), ((3, 3), 32, 2, 0.1),
+                                                  ((2, 4), 16, 2, 0.02), ((1, 6), 8, 3, 0.06),
+                                                  ((3, 3), 32, 1, 0.0)])
+def test_xy_full_chi_matches_state_vector(shape, chi, steps, tau):
+    """Neel state, Trotterised preparation and staggered phase, depth-7
+    steps: at full bond dimension the exact state, the X^2 signal and the
+    conserved charge."""
+    from oracle.xy import XYGrid, XYStateVector
+    g = XYGrid(*shape)
+    sim = mpsim.Simulation(mpsim.make_xy_config(shape[0], shape[1], chi, XY_G, XY_DT,
+                                                tau * math.pi))
+    sv = XYStateVector(g, XY_G, XY_DT, tau * math.pi)
+    a, b = sim.measure(), sv.measure()
+    assert abs(a["z2"] - b["x2"]) < TOL and abs(a["z"] - b["z"]) < TOL
+    assert abs(abs(np.vdot(sv.psi, sim.to_statevector())) ** 2 - 1) < TOL
+    for _ in range(steps):
+        sim.step(1)
+        sv.step()
+        a, b = sim.measure(), sv.measure()
+        assert abs(a["z2"] - b["x2"]) < TOL
+        assert abs(a["z"] - b["z"]) < TOL
+        assert abs(a["log_fidelity"]) < 1e-11
+    assert abs(abs(np.vdot(sv.psi, sim.to_statevector())) ** 2 - 1) < TOL
+
+
+@pytest.mark.parametrize("shape,chi,steps,seed", [((4, 4), 8, 2, 81), ((3, 4), 6, 3, 82),
+                                                   ((5, 5), 16, 1, 83), ((6, 6), 24, 1, 85)])
+def test_xy_truncating_parity(shape, chi, steps, seed):
+    """Symmetry-free random start state (the Neel-based states have
+    degenerate cuts, so their truncations are not unique), truncating bond
+    dimension: X^2 signal, <Z_tot>, log F and every per-update fidelity agree
+    with the oracle."""
+    from oracle.xy import XYGrid, XYMPS
+    g = XYGrid(*shape)
+    n = g.n
+    sites, centre = workloads.random_mps(shape[0], shape[1], chi, seed, dims=[2] * n)
+    sim = mpsim.Simulation(mpsim.make_xy_config(shape[0], shape[1], chi, XY_G, XY_DT, 0.0))
+    sim.set_state(sites, centre)
+    ora = XYMPS(g, chi, XY_G, XY_DT, 0.0)
+    ora.sites = [np.array(s_, dtype=np.complex128) for s_ in sites]
+    ora.centre = centre
+    ora.log_fidelity = 0.0
+    ora.update_log = []
+    for _ in range(steps):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        print(shape, chi, "x2 err", abs(a["z2"] - b["x2"]), "logF err",
+              abs(a["log_fidelity"] - b["log_fidelity"]))
+        assert abs(a["z2"] - b["x2"]) < TOL and abs(a["z"] - b["z"]) < TOL
+        assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert len(f_gpu) == len(f_ora)
+    assert np.max(np.abs(f_gpu - f_ora)) < TOL
+    assert sim.bond_dims() == ora.bond_dims()
