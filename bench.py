@@ -253,6 +253,37 @@ def cube_rate(shape: tuple[int, int, int], chi: int, precision: str, steps: int,
             "steps_per_s": steps / el, "z": obs["z"], "fidelity": obs["fidelity"]}
 
 
+def xy_rate(shape: tuple[int, int], chi: int, precision: str, steps: int, seed: int) -> dict:
+    """Trotter steps/s of the XY-model quench (one qubit per site, open
+    boundaries, depth-7 second-order steps with every bond routed and
+    returned) from a seeded random MPS at saturated bonds; each step includes
+    one measurement of the X^2 signal and the charge."""
+    import torch
+    from paper_2511_23438_amd import mpsim, workloads
+    lx, ly = shape
+    n = lx * ly
+    cfg = mpsim.make_xy_config(lx, ly, chi, precision=precision)
+    sim = mpsim.Simulation(cfg)
+    sites, centre = workloads.random_mps(lx, ly, chi, seed, dims=[2] * n)
+    sim.set_state(sites, centre)
+    del sites
+    ops = mpsim.schedule_dump(cfg, 1)
+    nu2 = int(sum(1 for r in ops if r[0] == 1))
+    ngate = int(sum(1 for r in ops if r[0] == 1 and r[3] != 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(1)
+        obs = sim.measure()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.free()
+    return {"workload": "xy_%dx%d_chi%d" % (lx, ly, chi), "qubits": n,
+            "two_site_updates_per_step": nu2, "gated_updates_per_step": ngate, "steps": steps,
+            "seconds": el, "steps_per_s": steps / el, "x2": obs["z2"], "z": obs["z"],
+            "fidelity": obs["fidelity"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +312,10 @@ def main() -> int:
                     help="also time the cubic lattice LX,LY,LZ (one qubit per site)")
     ap.add_argument("--cube-chi", type=int, default=64)
     ap.add_argument("--cube-steps", type=int, default=2)
+    ap.add_argument("--xy", default="",
+                    help="also time the XY-model quench on the LX,LY grid")
+    ap.add_argument("--xy-chi", type=int, default=256)
+    ap.add_argument("--xy-steps", type=int, default=1)
     ap.add_argument("--instances", type=int, default=0,
                     help="also time this many concurrent instances of the workload")
     args = ap.parse_args()
@@ -408,6 +443,11 @@ def main() -> int:
         log("cube run: %s chi %d" % (shape, args.cube_chi))
         out["cube"] = cube_rate(shape, args.cube_chi, args.precision, args.cube_steps, args.seed)
         log("cube: %.3f steps/s" % out["cube"]["steps_per_s"])
+    if args.xy:
+        shape = tuple(int(v) for v in args.xy.split(","))
+        log("XY run: %s chi %d" % (shape, args.xy_chi))
+        out["xy"] = xy_rate(shape, args.xy_chi, args.precision, args.xy_steps, args.seed)
+        log("xy: %.3f steps/s" % out["xy"]["steps_per_s"])
     if args.instances > 0:
         log("concurrent run: %d instances" % args.instances)
         out["concurrent"] = concurrent(args.rows, args.cols, args.chi, args.precision,
