@@ -207,6 +207,14 @@ mps_status mps_set_state(mps_handle h, const int32_t* bonds, const double* const
  * truncations, not two-site contractions). */
 mps_status mps_apply_two_site(mps_handle h, int32_t site, int32_t swap, int32_t gate);
 
+/* As mps_apply_two_site, with the site of the next update as the hint the
+ * step loop uses when both sides of theta have the same size: next_site >= 0
+ * and < site keeps the orthogonality centre on `site` (the Gram matrix of
+ * the columns is used), anything else moves it to site+1 (the rows). For
+ * tests of both truncation sides. */
+mps_status mps_apply_two_site_toward(mps_handle h, int32_t site, int32_t swap, int32_t gate,
+                                     int32_t next_site);
+
 /* Per-update truncation fidelities f and relative gaps since init (or
  * mps_set_state), in order; *len receives the count. Synchronises. */
 mps_status mps_truncation_log(mps_handle h, double* f, double* gap, int32_t cap,

@@ -16,6 +16,13 @@ void launch_mpo_site(const cplx* src, cplx* dst, int b0, int d, int b1, int mode
 void launch_theta_gate4(cplx* theta, int b0, int b2, const cplx* G, int swap, hipStream_t s);
 // measurement with sign * X on a d = 2 site (see launch_meas_combine)
 void launch_meas_combine_x(cplx* X, int b, int b2, double sign, hipStream_t s);
+// factored Gram weights and the oriented d x d phase table (see the kernel)
+void launch_pair_weights(const cplx* table, int trans, int d, int side, cplx* W, cplx* Dfull,
+                         hipStream_t s);
+// rows ordered (s, a) -> (a, s): U[(a d + s) q + j] = Up[(s b0 + a) q + j]
+void launch_unpermute_rows(const cplx* Up, cplx* U, int b0, int d, int q, hipStream_t s);
+// *dst = sum_i Re G[i, i]
+void launch_trace_real(const cplx* G, long n, long ldg, double* dst, hipStream_t s);
 // dst[slot] = sum |x|^2 over len entries (deterministic two-pass reduction).
 void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStream_t s);
 // Truncation bookkeeping: f = sc[3]/sc[2], sc[0] += log f, sc[4] = 1/sqrt(sc[3]),

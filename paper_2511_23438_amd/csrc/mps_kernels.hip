@@ -133,6 +133,68 @@ void launch_meas_combine_x(cplx* X, int b, int b2, double sign, hipStream_t s) {
   hipLaunchKernelGGL(k_meas_combine_x, dim3(std::max(blocks, 1)), dim3(256), 0, s, X, b, b2, sign);
 }
 
+// Weights of the factored Gram matrix of a two-site update without SWAP.
+// Dfull[s1][s2] = D[s1][s2] (the block-pair phase table, stored [s_a][s_b]
+// for the lower block id a; trans when the lower id sits at site i+1; all
+// ones without a gate). side 0 (rows of theta): W[pidx(s1, s1')][s2] =
+// D[s1][s2] conj(D[s1'][s2]); side 1 (columns): W[pidx(s2, s2')][s1] =
+// conj(D[s1][s2]) D[s1][s2']; pidx(x, y) = x (x + 1) / 2 + y for y <= x.
+__global__ void k_pair_weights(const cplx* table, int trans, int d, int side, cplx* W, cplx* Dfull) {
+  const int t = threadIdx.x;
+  for (int e = t; e < d * d; e += blockDim.x) {
+    const int s1 = e / d, s2 = e % d;
+    Dfull[e] = table ? (trans ? table[s2 * d + s1] : table[s1 * d + s2]) : make_double2(1.0, 0.0);
+  }
+  __syncthreads();
+  const int np = d * (d + 1) / 2;
+  for (int e = t; e < np * d; e += blockDim.x) {
+    const int p = e / d, k = e % d;
+    int x = 0;
+    while ((x + 1) * (x + 2) / 2 <= p) ++x;
+    const int y = p - x * (x + 1) / 2;
+    cplx w;
+    if (side == 0) w = cmulc(Dfull[y * d + k], Dfull[x * d + k]);   // D[x][k] conj(D[y][k])
+    else w = cmulc(Dfull[k * d + x], Dfull[k * d + y]);             // conj(D[k][x]) D[k][y]
+    W[e] = w;
+  }
+}
+
+void launch_pair_weights(const cplx* table, int trans, int d, int side, cplx* W, cplx* Dfull,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_weights, dim3(1), dim3(256), 0, s, table, trans, d, side, W, Dfull);
+}
+
+// U[(a d + s) q + j] = Up[(s b0 + a) q + j]: rows ordered (s, a) back to (a, s)
+__global__ void k_unpermute_rows(const cplx* Up, cplx* U, int b0, int d, int q) {
+  const long total = (long)b0 * d * q;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long row = idx / q, j = idx % q;
+    const long a = row / d, sidx = row % d;
+    U[idx] = Up[(sidx * b0 + a) * q + j];
+  }
+}
+
+void launch_unpermute_rows(const cplx* Up, cplx* U, int b0, int d, int q, hipStream_t s) {
+  const long total = (long)b0 * d * q;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_unpermute_rows, dim3(std::max(blocks, 1)), dim3(256), 0, s, Up, U, b0, d, q);
+}
+
+// dst = sum of the real parts of the n diagonal entries of G (ld ldg), one
+// workgroup, fixed summation order
+__global__ __launch_bounds__(256) void k_trace_real(const cplx* G, long n, long ldg, double* dst) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) acc += G[i * ldg + i].x;
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) *dst = acc;
+}
+
+void launch_trace_real(const cplx* G, long n, long ldg, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace_real, dim3(1), dim3(256), 0, s, G, n, ldg, dst);
+}
+
 void launch_apply_u1(cplx* site, int b0, int d, int b1, const cplx* U, hipStream_t s) {
   long pairs = (long)b0 * b1;
   int blocks = (int)std::min<long>((pairs + 255) / 256, 4096);

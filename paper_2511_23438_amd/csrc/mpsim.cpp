@@ -62,6 +62,7 @@ struct mps_sim {
   cplx* d_gates = nullptr;
   std::vector<long> gate_off[4];
   cplx* d_xy = nullptr;  // XY model: gates 1..4, 16 complex each
+  cplx* d_wt = nullptr;  // factored Gram: weights (<= 136 x 16) and the oriented phase table
   double* d_zsum = nullptr;
   std::vector<long> zsum_off;
 
@@ -313,6 +314,141 @@ void heev(mps_sim* h, int kg, int q, cplx* U, uint64_t seed) {
     heev_top(kg, h->gram, kg, q, U, q, h->tmpA, h->lw, seed, h->stream);
 }
 
+// Two-site update without SWAP through the factored Gram matrix. With
+// theta[(a s1), (s2 c)] = D[s1][s2] (A_s1 B_s2)[a, c] (A_s1: rows a d + s1 of
+// site i, B_s2: columns s2 b2 + c of site i+1), the Gram matrix on the rows,
+// taken in the order (s1, a), has the blocks
+//   G_{s1 s1'} = A_s1 (sum_s2 D[s1][s2] conj(D[s1'][s2]) B_s2 B_s2^H) A_s1'^H,
+// and the one on the columns
+//   G_{s2 s2'} = B_s2^H (sum_s1 conj(D[s1][s2]) D[s1][s2'] A_s1^H A_s1) B_s2';
+// the truncation products factor the same way (C = U^H theta from
+// U_s1^H A_s1, C = theta V from B_s2 V_s2), so theta is never formed and the
+// Gram costs two chi^3 products per block pair instead of d chi^3.
+// Returns false (nothing done) when the shape does not qualify.
+bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t seed) {
+  const Plan& p = h->plan;
+  const int ba = h->pos[i], bb = h->pos[i + 1];
+  const int d = p.dim(ba);
+  if (p.dim(bb) != d || d < 4 || h->gprec != GEMM_F64 || p.model != 0) return false;
+  const long b0 = h->bond[i], b1 = h->bond[i + 1], b2 = h->bond[i + 2];
+  const long kg = left ? b0 * d : (long)d * b2;
+  if (kg < MPS_EIG2_MIN) return false;
+  const long np = (long)d * (d + 1) / 2;
+  if ((long)(d + np) * b1 * b1 > h->theta_elems) return false;
+  hipStream_t s = h->stream;
+  const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
+  cplx* A = h->site[i];
+  cplx* B = h->site[i + 1];
+  const long lda = (long)d * b1, ldb = (long)d * b2;
+  const cplx* table = nullptr;
+  int trans = 0;
+  if (gate) {
+    const int pi = p.coupled(ba, bb);
+    if (pi >= 0) {
+      table = h->d_pairs + h->pair_off[pi];
+      trans = (ba > bb) ? 1 : 0;
+    }
+  }
+  cplx* W = h->d_wt;
+  cplx* Dfull = h->d_wt + 136 * 16;
+  launch_pair_weights(table, trans, d, left ? 0 : 1, W, Dfull, s);
+  cplx* Mb = h->theta;                      // d products, b1 x b1 each
+  cplx* Kb = h->theta + (long)d * b1 * b1;  // np weighted sums, b1 x b1 each
+  const int extra = (q < kg) ? 1 : 0;
+  if (left) {
+    // M_s2 = B_s2 B_s2^H
+    ZGemm gm = zgemm_args((int)b1, (int)b1, (int)b2, zop(B, ldb, 0), zop(B, ldb, 1, 1), Mb, b1, 0, one, zero);
+    gm.batch = d; gm.A.stride = b2; gm.B.stride = b2; gm.strideC = b1 * b1;
+    zgemm(gm, nullptr, 0, s, &h->prof);
+  } else {
+    // N_s1 = A_s1^H A_s1
+    ZGemm gm = zgemm_args((int)b1, (int)b1, (int)b0, zop(A, lda, 1, 1), zop(A, lda, 0), Mb, b1, 0, one, zero);
+    gm.batch = d; gm.A.stride = b1; gm.B.stride = b1; gm.strideC = b1 * b1;
+    zgemm(gm, nullptr, 0, s, &h->prof);
+  }
+  // weighted sums of all block pairs at once: (np x d) (d x b1^2)
+  ZGemm gk = zgemm_args((int)np, (int)(b1 * b1), d, zop(W, d, 0), zop(Mb, b1 * b1, 0), Kb, b1 * b1, 0, one,
+                        zero);
+  zgemm(gk, nullptr, 0, s, &h->prof);
+  // Gram blocks (lower block triangle, diagonal blocks in full), column-major
+  for (int x = 0; x < d; ++x) {
+    cplx* Kx = Kb + (long)x * (x + 1) / 2 * b1 * b1;
+    if (left) {
+      // T_y = A_x K_xy (b0 x b1), G_xy = T_y A_y^H
+      ZGemm gt = zgemm_args((int)b0, (int)b1, (int)b1, zop(A + (long)x * b1, lda, 0), zop(Kx, b1, 0), h->tmpA,
+                            b1, 0, one, zero);
+      gt.batch = x + 1; gt.A.stride = 0; gt.B.stride = b1 * b1; gt.strideC = b0 * b1;
+      zgemm(gt, nullptr, 0, s, &h->prof);
+      ZGemm gg = zgemm_args((int)b0, (int)b0, (int)b1, zop(h->tmpA, b1, 0), zop(A, lda, 1, 1),
+                            h->gram + (long)x * b0, kg, 1, one, zero);
+      gg.batch = x + 1; gg.A.stride = b0 * b1; gg.B.stride = b1; gg.strideC = b0 * kg;
+      gg.tag = PROF_GRAM;
+      zgemm(gg, nullptr, 0, s, &h->prof);
+    } else {
+      // T_y = B_x^H L_xy (b2 x b1), G_xy = T_y B_y
+      ZGemm gt = zgemm_args((int)b2, (int)b1, (int)b1, zop(B + (long)x * b2, ldb, 1, 1), zop(Kx, b1, 0),
+                            h->tmpA, b1, 0, one, zero);
+      gt.batch = x + 1; gt.A.stride = 0; gt.B.stride = b1 * b1; gt.strideC = b2 * b1;
+      zgemm(gt, nullptr, 0, s, &h->prof);
+      ZGemm gg = zgemm_args((int)b2, (int)b2, (int)b1, zop(h->tmpA, b1, 0), zop(B, ldb, 0),
+                            h->gram + (long)x * b2, kg, 1, one, zero);
+      gg.batch = x + 1; gg.A.stride = b2 * b1; gg.B.stride = b2; gg.strideC = b2 * kg;
+      gg.tag = PROF_GRAM;
+      zgemm(gg, nullptr, 0, s, &h->prof);
+    }
+  }
+  launch_trace_real(h->gram, kg, kg, h->dscal + 2, s);
+  heev(h, (int)kg, q, h->tmpB, seed);
+  ensure_log(h, h->nlog + 1);
+  if (left) {
+    // P_s1 = U_s1^H A_s1 (q x b1), U in (s1, a) row order
+    ZGemm gp = zgemm_args(q, (int)b1, (int)b0, zop(h->tmpB, q, 1, 1), zop(A, lda, 0), h->tmpC, b1, 0, one,
+                          zero);
+    gp.batch = d; gp.A.stride = b0 * q; gp.B.stride = b1; gp.strideC = (long)q * b1;
+    zgemm(gp, nullptr, 0, s, &h->prof);
+    // Q_s2 = sum_s1 D[s1][s2] P_s1: (d x d)^T (d x q b1)
+    ZGemm gq = zgemm_args(d, (int)(q * b1), d, zop(Dfull, d, 1), zop(h->tmpC, q * b1, 0), h->tmpA, q * b1, 0,
+                          one, zero);
+    zgemm(gq, nullptr, 0, s, &h->prof);
+    // C_s2 = Q_s2 B_s2 -> columns s2 b2 .. of C (q x d b2)
+    ZGemm gc = zgemm_args(q, (int)b2, (int)b1, zop(h->tmpA, b1, 0), zop(B, ldb, 0), h->theta, ldb, 0, one,
+                          zero);
+    gc.batch = d; gc.A.stride = (long)q * b1; gc.B.stride = b2; gc.strideC = b2;
+    zgemm(gc, nullptr, 0, s, &h->prof);
+    launch_unpermute_rows(h->tmpB, A, (int)b0, d, q, s);
+    norm2(h, h->theta, (long)q * ldb, 3);
+    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_scale_by(h->theta, (long)q * ldb, h->dscal, s);
+    HIPCHK(hipMemcpyAsync(B, h->theta, sizeof(cplx) * (size_t)q * ldb, hipMemcpyDeviceToDevice, s));
+    h->centre = i + 1;
+  } else {
+    // R_s2 = B_s2 V_s2 (b1 x q), V in natural (s2, c) row order
+    ZGemm gr = zgemm_args((int)b1, q, (int)b2, zop(B, ldb, 0), zop(h->tmpB, q, 0), h->tmpC, q, 0, one, zero);
+    gr.batch = d; gr.A.stride = b2; gr.B.stride = b2 * q; gr.strideC = b1 * q;
+    zgemm(gr, nullptr, 0, s, &h->prof);
+    // Q_s1 = sum_s2 D[s1][s2] R_s2: (d x d) (d x b1 q)
+    ZGemm gq = zgemm_args(d, (int)(b1 * q), d, zop(Dfull, d, 0), zop(h->tmpC, b1 * q, 0), h->tmpA, b1 * q, 0,
+                          one, zero);
+    zgemm(gq, nullptr, 0, s, &h->prof);
+    // C_s1 = A_s1 Q_s1 -> rows a d + s1 of C (b0 d x q)
+    ZGemm gc = zgemm_args((int)b0, q, (int)b1, zop(A, lda, 0), zop(h->tmpA, q, 0), h->theta, (long)d * q, 0,
+                          one, zero);
+    gc.batch = d; gc.A.stride = b1; gc.B.stride = b1 * q; gc.strideC = q;
+    zgemm(gc, nullptr, 0, s, &h->prof);
+    // site i+1 = V^H (q x d b2)
+    launch_conj_transpose(h->tmpB, (int)kg, q, q, B, kg, s);
+    norm2(h, h->theta, b0 * d * q, 3);
+    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_scale_by(h->theta, b0 * d * q, h->dscal, s);
+    HIPCHK(hipMemcpyAsync(A, h->theta, sizeof(cplx) * (size_t)(b0 * d * q), hipMemcpyDeviceToDevice, s));
+    h->centre = i;
+  }
+  h->nlog += 1;
+  h->nupdates += 1;
+  h->bond[i + 1] = q;
+  return true;
+}
+
 void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   const Plan& p = h->plan;
   if (h->centre < i) move_centre(h, i);
@@ -323,6 +459,11 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   const long m = (long)b0 * d1, n = (long)d2 * b2;
   const long mo = swap ? (long)b0 * d2 : m, no = swap ? (long)d1 * b2 : n;
   const int q = (int)std::min<long>(p.chi, std::min(mo, no));
+  bool left;
+  if (mo != no) left = mo < no;
+  else left = !(next_site >= 0 && next_site < i);
+  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->nupdates;
+  if (!swap && two_site_factored(h, i, gate, left, q, seed)) return;
 
   // theta
   ZGemm g = zgemm_args((int)m, (int)n, b1, zop(h->site[i], b1, 0), zop(h->site[i + 1], n, 0), h->theta,
@@ -345,10 +486,6 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   if (dense_gate) launch_theta_gate4(h->theta, b0, b2, h->d_xy + 16 * gate, swap, s);
   norm2(h, h->theta, mo * no, 2);
 
-  bool left;
-  if (mo != no) left = mo < no;
-  else left = !(next_site >= 0 && next_site < i);
-  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->nupdates;
   const int extra = (q < (left ? mo : no)) ? 1 : 0;
   const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
   if (left) {
@@ -691,6 +828,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->site.resize(p.N);
     for (int s = 0; s < p.N; ++s) h->site[s] = dalloc<cplx>(h, (long)p.xcap[s] * p.dmax * p.xcap[s + 1]);
     h->theta = dalloc<cplx>(h, z.theta);
+    h->theta_elems = z.theta;
     h->gram = dalloc<cplx>(h, z.gram);
     h->tmpA = dalloc<cplx>(h, z.tmp);
     h->tmpB = dalloc<cplx>(h, z.tmp);
@@ -770,6 +908,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     }
     h->d_zsum = dalloc<double>(h, (long)hz.size());
     HIPCHK(copy_sync(h, h->d_zsum, hz.data(), sizeof(double) * hz.size(), hipMemcpyHostToDevice));
+    h->d_wt = dalloc<cplx>(h, 136 * 16 + 256);
     if (p.model == 1) {
       std::vector<cplx> hx(5 * 16, make_double2(0.0, 0.0));
       for (int v = 1; v <= 4; ++v)
@@ -973,6 +1112,16 @@ mps_status mps_apply_two_site(mps_handle h, int32_t site, int32_t swap, int32_t 
   if (h->plan.schedule == 4)
     return fail(h, MPS_E_UNSUPPORTED, "two-site updates are not sized for the gate-by-gate schedule");
   TRYDEV(h, two_site(h, site, swap ? 1 : 0, gate ? 1 : 0, -1); HIPCHK(hipGetLastError()));
+  return MPS_OK;
+}
+
+mps_status mps_apply_two_site_toward(mps_handle h, int32_t site, int32_t swap, int32_t gate,
+                                     int32_t next_site) {
+  GUARD(h);
+  if (site < 0 || site + 1 >= h->plan.N) return fail(h, MPS_E_INVAL, "bad site");
+  if (h->plan.schedule == 4)
+    return fail(h, MPS_E_UNSUPPORTED, "two-site updates are not sized for the gate-by-gate schedule");
+  TRYDEV(h, two_site(h, site, swap ? 1 : 0, gate ? 1 : 0, next_site); HIPCHK(hipGetLastError()));
   return MPS_OK;
 }
 

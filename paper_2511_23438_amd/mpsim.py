@@ -86,6 +86,7 @@ _sig = {
     "mps_set_state": (C.c_int, [H, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_double)),
                                 C.c_int32]),
     "mps_apply_two_site": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32]),
+    "mps_apply_two_site_toward": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "mps_truncation_log": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.c_int32, C.POINTER(C.c_int32)]),
     "mps_to_statevector": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64]),
@@ -310,8 +311,11 @@ class Simulation:
             *[k.ctypes.data_as(C.POINTER(C.c_double)) for k in keep])
         _check(_lib.mps_set_state(self.h, bb, ptrs, centre), self.h)
 
-    def apply_two_site(self, site: int, swap: bool, gate: bool) -> None:
-        _check(_lib.mps_apply_two_site(self.h, site, int(swap), int(gate)), self.h)
+    def apply_two_site(self, site: int, swap: bool, gate: bool, next_site: int = -1) -> None:
+        """One two-site update; next_site is the step loop's hint for equal
+        sides (a next update left of `site` keeps the centre on `site`)."""
+        _check(_lib.mps_apply_two_site_toward(self.h, site, int(swap), int(gate), int(next_site)),
+               self.h)
 
     def truncation_log(self) -> tuple[np.ndarray, np.ndarray]:
         n = C.c_int32()
