@@ -292,7 +292,8 @@ def main() -> int:
     ap.add_argument("--start", default="random", choices=["random", "product"])
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--pmc-sample", action="store_true",
-                    help="counter sample: a 1 GiB elementwise kernel, then one bulk two-site update")
+                    help="counter sample: a 1 GiB elementwise kernel, then one bulk two-site "
+                         "update with SWAP (direct Gram matrix)")
     ap.add_argument("--rows", type=int, default=6)
     ap.add_argument("--cols", type=int, default=8)
     ap.add_argument("--chi", type=int, default=1024)
@@ -350,7 +351,7 @@ def main() -> int:
         torch.cuda.synchronize()
         log("calibration kernel (1 GiB read, 1 GiB written) done")
         t0 = time.perf_counter()
-        sim.apply_two_site(args.rows - 1, 0, 1)
+        sim.apply_two_site(args.rows - 1, 1, 1)
         sim.sync()
         log("bulk update done in %.2fs" % (time.perf_counter() - t0))
         print(json.dumps({"pmc_sample": True, "workload": "tfim_%dx%d_chi%d" % (

@@ -570,7 +570,6 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
                   make_double2((double)cr[a][b][v], (double)ci[a][b][v]));
 }
 
-// Sum the split-K partials and apply the store epilogue.
 // ---------------------------------------------------------------------------
 // Hermitian operand (lower triangle stored column-major) times a narrow
 // operand of at most 32 columns: 128 x 32 outputs per workgroup, each wave
@@ -727,6 +726,7 @@ __global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
                                t3[a][b][v] - t1[a][b][v] - t2[a][b][v]));
 }
 
+// Sum the split-K partials and apply the store epilogue.
 __global__ void zgemm_reduce(ZGemmDev gd) {
   const ZGemm& g = gd.g;
   long total = (long)g.M * g.N;
@@ -735,8 +735,16 @@ __global__ void zgemm_reduce(ZGemmDev gd) {
        e += (long)gridDim.x * blockDim.x) {
     long row = e / g.N, col = e % g.N;
     cplx s = make_double2(0, 0);
-    for (int k = 0; k < gd.ksplit; ++k)
-      s = cadd(s, gd.partial[((long)(bat * gd.ksplit + k) * g.M + row) * g.N + col]);
+    // 16 loads in flight per round; summation order k = 0, 1, ... as a plain loop
+    for (int k0 = 0; k0 < gd.ksplit; k0 += 16) {
+      cplx pv[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        pv[i] = (k0 + i < gd.ksplit) ? gd.partial[((long)(bat * gd.ksplit + k0 + i) * g.M + row) * g.N + col]
+                                     : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s = cadd(s, pv[i]);
+    }
     cplx* C = g.C + (long)bat * g.strideC;
     const long idx = g.transC ? col * g.ldc + row : row * g.ldc + col;
     cplx out = cmul(g.alpha, s);
@@ -783,12 +791,15 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(256), 0, s, z);
     return;
   }
-  // split-K for skinny outputs; the Hermitian product (a few column tiles
-  // over a long K) is split until about 1024 workgroups run
-  const long want = g.herm_a ? 1024 : 256;
+  // split-K for skinny outputs, until about 1024 workgroups run (four per
+  // CU, so that operand loads overlap), in chunks of at least 256 (64 for a
+  // handful of output tiles, whose K loop would otherwise run on a few dozen
+  // workgroups)
+  const long want = 1024;
+  const long kmin = tiles <= 4 ? 64 : 256;
   if (partial && g.epi == EPI_STORE && !g.lower_only && !g.upper_only && !g.kcat &&
-      (tiles < 128 || g.herm_a) && g.K >= 1024) {
-    int ks = (int)std::min<long>(g.K / 256, (want + tiles - 1) / tiles);
+      (tiles < 128 || g.herm_a) && g.K >= 4 * kmin) {
+    int ks = (int)std::min<long>(g.K / kmin, (want + tiles - 1) / tiles);
     while (ks > 1 && (long)ks * g.batch * g.M * g.N > partial_elems) --ks;
     if (ks > 1) {
       gd.ksplit = ks;
