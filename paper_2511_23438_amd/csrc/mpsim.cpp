@@ -324,12 +324,14 @@ void heev(mps_sim* h, int kg, int q, cplx* U, uint64_t seed) {
 // the truncation products factor the same way (C = U^H theta from
 // U_s1^H A_s1, C = theta V from B_s2 V_s2), so theta is never formed and the
 // Gram costs two chi^3 products per block pair instead of d chi^3.
+// The Gram products run in float64 whatever the precision mode; the
+// products that form C take the mode's contraction precision.
 // Returns false (nothing done) when the shape does not qualify.
 bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t seed) {
   const Plan& p = h->plan;
   const int ba = h->pos[i], bb = h->pos[i + 1];
   const int d = p.dim(ba);
-  if (p.dim(bb) != d || d < 4 || h->gprec != GEMM_F64 || p.model != 0) return false;
+  if (p.dim(bb) != d || d < 4 || p.model != 0) return false;
   const long b0 = h->bond[i], b1 = h->bond[i + 1], b2 = h->bond[i + 2];
   const long kg = left ? b0 * d : (long)d * b2;
   if (kg < MPS_EIG2_MIN) return false;
@@ -405,6 +407,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     ZGemm gp = zgemm_args(q, (int)b1, (int)b0, zop(h->tmpB, q, 1, 1), zop(A, lda, 0), h->tmpC, b1, 0, one,
                           zero);
     gp.batch = d; gp.A.stride = b0 * q; gp.B.stride = b1; gp.strideC = (long)q * b1;
+    gp.prec = h->gprec;
     zgemm(gp, nullptr, 0, s, &h->prof);
     // Q_s2 = sum_s1 D[s1][s2] P_s1: (d x d)^T (d x q b1)
     ZGemm gq = zgemm_args(d, (int)(q * b1), d, zop(Dfull, d, 1), zop(h->tmpC, q * b1, 0), h->tmpA, q * b1, 0,
@@ -414,6 +417,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     ZGemm gc = zgemm_args(q, (int)b2, (int)b1, zop(h->tmpA, b1, 0), zop(B, ldb, 0), h->theta, ldb, 0, one,
                           zero);
     gc.batch = d; gc.A.stride = (long)q * b1; gc.B.stride = b2; gc.strideC = b2;
+    gc.prec = h->gprec;
     zgemm(gc, nullptr, 0, s, &h->prof);
     launch_unpermute_rows(h->tmpB, A, (int)b0, d, q, s);
     norm2(h, h->theta, (long)q * ldb, 3);
@@ -425,6 +429,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     // R_s2 = B_s2 V_s2 (b1 x q), V in natural (s2, c) row order
     ZGemm gr = zgemm_args((int)b1, q, (int)b2, zop(B, ldb, 0), zop(h->tmpB, q, 0), h->tmpC, q, 0, one, zero);
     gr.batch = d; gr.A.stride = b2; gr.B.stride = b2 * q; gr.strideC = b1 * q;
+    gr.prec = h->gprec;
     zgemm(gr, nullptr, 0, s, &h->prof);
     // Q_s1 = sum_s2 D[s1][s2] R_s2: (d x d) (d x b1 q)
     ZGemm gq = zgemm_args(d, (int)(b1 * q), d, zop(Dfull, d, 0), zop(h->tmpC, b1 * q, 0), h->tmpA, b1 * q, 0,
@@ -434,6 +439,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     ZGemm gc = zgemm_args((int)b0, q, (int)b1, zop(A, lda, 0), zop(h->tmpA, q, 0), h->theta, (long)d * q, 0,
                           one, zero);
     gc.batch = d; gc.A.stride = b1; gc.B.stride = b1 * q; gc.strideC = q;
+    gc.prec = h->gprec;
     zgemm(gc, nullptr, 0, s, &h->prof);
     // site i+1 = V^H (q x d b2)
     launch_conj_transpose(h->tmpB, (int)kg, q, q, B, kg, s);

@@ -523,3 +523,22 @@ def test_factored_gram_matches_oracle(eig_path):
     assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
     assert abs(a["log_fidelity"] - b["log_fidelity"]) < TOL
     assert sim.bond_dims() == ora.bond_dims()
+
+
+@pytest.mark.parametrize("prec", ["c64", "bf16x3"])
+def test_factored_gram_reduced_precision(prec):
+    """Factored Gram path with reduced-precision contractions (the Gram
+    products stay float64): within 1e-5 of the float64 oracle."""
+    sites, centre = workloads.random_mps(6, 8, 128, 91, centre=3)
+    sim = mpsim.Simulation(mpsim.make_config(6, 8, 128, theta0=0.0, schedule=2, precision=prec))
+    sim.set_state(sites, centre)
+    ora = omps.BlockMPS.from_sites(Grid(6, 8), 128, sites, centre, J, H, DT, schedule=2)
+    for (i, sw, gt, nxt) in [(3, 0, 1, 5), (5, 0, 1, 7), (7, 0, 1, 0)]:
+        sim.apply_two_site(i, sw, gt, nxt)
+        ora.apply_u2(i, bool(sw), bool(gt))
+    f_gpu, _ = sim.truncation_log()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert np.max(np.abs(f_gpu - f_ora) / f_ora) < 1e-5
+    a, b = sim.measure(), ora.measure()
+    print(prec, "z err %.2e z2 err %.2e" % (abs(a["z"] - b["z"]), abs(a["z2"] - b["z2"])))
+    assert abs(a["z"] - b["z"]) < 1e-5 and abs(a["z2"] - b["z2"]) < 1e-5
