@@ -40,8 +40,6 @@ struct LinalgWork {
   double* e2 = nullptr;     // squared off-diagonal (nmax)
   cplx* dpart = nullptr;    // partial dot products (column steps)
   cplx* tsum = nullptr;     // reduced column-step sums (2*TRD_NB + 1)
-  int* cnt = nullptr;       // completion counters (zero between launches)
-  long cnt_stride = 0;      // offset of the column-kernel counter in cnt
   double* npart = nullptr;  // partial norms (QR column steps)
   double* scal = nullptr;   // 16 doubles of scalars
   double* lam = nullptr;    // eigenvalues (qmax + 1), ascending

@@ -51,15 +51,7 @@ static ZOp strided_op(const cplx* base, long rs, long cs, int conj = 0) {
 // scal: [0] beta [1,2] tau [3,4] scale of the latest column.
 #define TP (2 * TRD_NB + 1)
 // workgroups of the mat-vec kernel; each loops over tiles
-#ifndef HEMV_WGS
-#define HEMV_WGS 2048
-#endif
-#ifndef HEMV_VARIANT
-#define HEMV_VARIANT 0
-#endif
-#ifndef HEMV_PIPE_OCC
-#define HEMV_PIPE_OCC 2
-#endif
+constexpr int HEMV_WGS = 2048;
 
 // alpha = -(tau/2) * sum of the partial dot products y^H v of the previous
 // column, reduced by the whole workgroup (every thread must call it).
@@ -261,11 +253,7 @@ __global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda
       }
     } else {
       const cplx vi = vI[rr];
-#if HEMV_VARIANT == 1
-#pragma unroll
-#else
 #pragma unroll 1
-#endif
       for (int g8 = 0; g8 < 2; ++g8) {
         cplx av[8];
 #pragma unroll
@@ -309,324 +297,6 @@ __global__ __launch_bounds__(256) void k_trd_hemv(int n, const cplx* A, long lda
     red[cg][rr] = y;
     __syncthreads();
     if (t < 64) P[(I * nt + J) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
-  }
-}
-
-// Strictly lower tile (I > J) for linear index k: column block J outer
-// (descending), row block I inner, so workgroups running together read
-// neighbouring segments of the same 64 columns.
-__device__ inline void trd_tile_off(long k, int nt, long& I, long& J) {
-  long a = (long)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
-  while (a * (a + 1) / 2 > k) --a;
-  while ((a + 1) * (a + 2) / 2 <= k) ++a;
-  const long b = k - a * (a + 1) / 2;
-  J = nt - 2 - a;
-  I = nt - 1 - b;
-}
-
-// Same product as k_trd_hemv, software-pipelined over the strictly lower
-// tiles: while a workgroup computes one tile from registers, the loads of its
-// next tile (and of the two reflector segments it needs) are in flight. The
-// nt diagonal tiles follow, one per workgroup.
-__global__ __launch_bounds__(256, HEMV_PIPE_OCC) void k_trd_hemv_pipe(int n, const cplx* A, long lda, int c, int j,
-                                                      const cplx* tpart, int nparts, cplx* tsum,
-                                                      double* scal, double* d, double* e, cplx* tau,
-                                                      cplx* P, int nt, long ntiles) {
-  __shared__ cplx vbuf[2][64];
-  __shared__ cplx red[4][64];
-  __shared__ cplx sc_s;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wq = t >> 6;
-  if (wq == 1) {
-    for (int k = 1 + blockIdx.x; k <= 2 * j; k += gridDim.x) {
-      cplx acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-      for (int b = lane; b < nparts; b += 64) acc = cadd(acc, tpart[(long)b * TP + k]);
-      acc.x = wave_sum(acc.x);
-      acc.y = wave_sum(acc.y);
-      if (lane == 0) tsum[k] = acc;
-    }
-  }
-  if (wq == 0) {
-    double xn = 0.0;
-#pragma unroll 4
-    for (int b = lane; b < nparts; b += 64) xn += tpart[(long)b * TP].x;
-    xn = wave_sum(xn);
-    if (lane == 0) {
-      double beta;
-      cplx tauv, scl;
-      reflector(A[(long)c * lda + c + 1], xn, beta, tauv, scl);
-      sc_s = scl;
-      if (blockIdx.x == 0) {
-        scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = scl.x; scal[4] = scl.y;
-        tau[c] = tauv;
-        e[c] = beta;
-        d[c] = A[(long)c * lda + c].x;
-      }
-    }
-  }
-  __syncthreads();
-  const int o = c + 1;
-  const cplx sc = sc_s;
-  const int rr = lane, cg = wq;
-  const long noff = ntiles - nt;
-  long k = blockIdx.x;
-  if (k < noff) {
-    // Loads are issued unconditionally so the compiler's wait counts can
-    // leave the next tile's loads in flight: rows past n (last row block)
-    // read row n-1 instead (their products meet zero entries of v and their
-    // sums are never used), and the last iteration re-reads its own tile.
-    long I, J;
-    trd_tile_off(k, nt, I, J);
-    const long n1 = (long)n - 1;
-    long rv = o + ((t < 64) ? I : J) * 64 + lane;
-    cplx vraw = A[(long)c * lda + std::min(rv, n1)];
-    cplx av[16];
-    {
-      const cplx* src = A + (o + J * 64 + cg * 16) * lda + std::min(o + I * 64 + rr, n1);
-#pragma unroll
-      for (int cc = 0; cc < 16; ++cc) av[cc] = src[cc * lda];
-    }
-    if (t < 128)
-      vbuf[t >> 6][lane] = (rv >= n) ? make_double2(0.0, 0.0)
-                                     : (rv == o) ? make_double2(1.0, 0.0) : cmul(vraw, sc);
-    __syncthreads();
-    while (true) {
-      const long kn = k + gridDim.x;
-      const bool more = kn < noff;
-      long In, Jn;
-      trd_tile_off(more ? kn : k, nt, In, Jn);
-      const long rvn = o + ((t < 64) ? In : Jn) * 64 + lane;
-      const cplx vnraw = A[(long)c * lda + std::min(rvn, n1)];
-      cplx an[16];
-      {
-        const cplx* src = A + (o + Jn * 64 + cg * 16) * lda + std::min(o + In * 64 + rr, n1);
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) an[cc] = src[cc * lda];
-      }
-      cplx y = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int cc = 0; cc < 16; ++cc) y = cadd(y, cmul(av[cc], vbuf[1][cg * 16 + cc]));
-      const cplx vi = vbuf[0][rr];
-#pragma unroll
-      for (int g8 = 0; g8 < 2; ++g8) {
-        cplx s8[8];
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) s8[cc] = cmulc(av[g8 * 8 + cc], vi);
-        // column sums over the 64 lanes: butterfly halving the values held
-        // per lane (8 -> 1), then three plain exchanges
-#pragma unroll
-        for (int half = 4, m = 32; half >= 1; half >>= 1, m >>= 1) {
-          const bool upper = (rr & m) != 0;
-#pragma unroll
-          for (int q2 = 0; q2 < half; ++q2) {
-            const cplx keep = upper ? s8[q2 + half] : s8[q2];
-            const cplx send = upper ? s8[q2] : s8[q2 + half];
-            cplx got;
-            got.x = __shfl_xor(send.x, m, 64);
-            got.y = __shfl_xor(send.y, m, 64);
-            s8[q2] = cadd(keep, got);
-          }
-        }
-        cplx z = s8[0];
-#pragma unroll
-        for (int m = 4; m >= 1; m >>= 1) {
-          z.x += __shfl_xor(z.x, m, 64);
-          z.y += __shfl_xor(z.y, m, 64);
-        }
-        if ((rr & 7) == 0) {
-          const int colid = ((rr >> 5) & 1) * 4 + ((rr >> 4) & 1) * 2 + ((rr >> 3) & 1);
-          P[(J * nt + I) * 64 + cg * 16 + g8 * 8 + colid] = z;
-        }
-      }
-      red[cg][rr] = y;
-      __syncthreads();
-      if (t < 64) P[(I * nt + J) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
-      if (!more) break;
-      if (t < 128)
-        vbuf[t >> 6][lane] = (rvn >= n) ? make_double2(0.0, 0.0)
-                                        : (rvn == o) ? make_double2(1.0, 0.0) : cmul(vnraw, sc);
-      __syncthreads();
-      k = kn;
-      I = In;
-      J = Jn;
-#pragma unroll
-      for (int cc = 0; cc < 16; ++cc) av[cc] = an[cc];
-    }
-  }
-  // diagonal tiles (Hermitian: the upper part from the stored lower triangle)
-  for (long Id = blockIdx.x; Id < nt; Id += gridDim.x) {
-    __syncthreads();
-    if (t < 64) vbuf[1][t] = trd_v(A, lda, n, c, o + Id * 64 + t, sc);
-    __syncthreads();
-    const long row = o + Id * 64 + rr;
-    cplx y = make_double2(0.0, 0.0);
-#pragma unroll 1
-    for (int cc = 0; cc < 16; ++cc) {
-      const int cl = cg * 16 + cc;
-      const long col = o + Id * 64 + cl;
-      cplx x = make_double2(0.0, 0.0);
-      if (row < n && col < n) {
-        if (cl < rr) x = A[col * lda + row];
-        else if (cl > rr) x = cconj(A[row * lda + col]);
-        else x = make_double2(A[col * lda + row].x, 0.0);
-      }
-      y = cadd(y, cmul(x, vbuf[1][cl]));
-    }
-    red[cg][rr] = y;
-    __syncthreads();
-    if (t < 64) P[(Id * nt + Id) * 64 + t] = cadd(cadd(red[0][t], red[1][t]), cadd(red[2][t], red[3][t]));
-  }
-}
-
-// y = A22 v with 512-thread workgroups: wave w of a tile covers its 64 rows
-// and columns 8w .. 8w+7. The strictly lower tiles come first (loads issued
-// before the reflector and the v segments they are multiplied with are
-// known), then the diagonal tiles.
-__global__ __launch_bounds__(512) void k_trd_hemv8(int n, const cplx* A, long lda, int c, int j,
-                                                  const cplx* tpart, int nparts, cplx* tsum,
-                                                  double* scal, double* d, double* e, cplx* tau,
-                                                  cplx* P, int nt, long ntiles) {
-  __shared__ cplx vbuf[2][64];
-  __shared__ cplx red[8][64];
-  __shared__ cplx sc_s;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wq = t >> 6;
-  const int o = c + 1;
-  const long n1 = (long)n - 1;
-  const long noff = ntiles - nt;
-  long k = blockIdx.x;
-  long I = 0, J = 0;
-  cplx av[8];
-  if (k < noff) {
-    trd_tile_off(k, nt, I, J);
-    const cplx* src = A + (o + J * 64 + wq * 8) * lda + std::min(o + I * 64 + lane, n1);
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) av[cc] = src[cc * lda];
-  }
-  if (wq == 1) {
-    // wave 1 of workgroup w reduces value 1 + w (+ grid multiples) of
-    // W^H x and V^H x (values 1..2j) for the finalising kernel
-    for (int kk = 1 + blockIdx.x; kk <= 2 * j; kk += gridDim.x) {
-      cplx acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-      for (int b = lane; b < nparts; b += 64) acc = cadd(acc, tpart[(long)b * TP + kk]);
-      acc.x = wave_sum(acc.x);
-      acc.y = wave_sum(acc.y);
-      if (lane == 0) tsum[kk] = acc;
-    }
-  }
-  if (wq == 0) {
-    // reflector of column c from |x|^2 (partials of the column kernel)
-    const cplx alpha = A[(long)c * lda + c + 1];
-    double xn = 0.0;
-#pragma unroll 4
-    for (int b = lane; b < nparts; b += 64) xn += tpart[(long)b * TP].x;
-    xn = wave_sum(xn);
-    if (lane == 0) {
-      double beta;
-      cplx tauv, scl;
-      reflector(alpha, xn, beta, tauv, scl);
-      sc_s = scl;
-      if (blockIdx.x == 0) {
-        scal[0] = beta; scal[1] = tauv.x; scal[2] = tauv.y; scal[3] = scl.x; scal[4] = scl.y;
-        tau[c] = tauv;
-        e[c] = beta;
-        d[c] = A[(long)c * lda + c].x;
-      }
-    }
-  }
-  __syncthreads();
-  const cplx sc = sc_s;
-  while (k < noff) {
-    if (t < 128) {
-      const long rv = o + ((t < 64) ? I : J) * 64 + lane;
-      const cplx raw = A[(long)c * lda + std::min(rv, n1)];
-      vbuf[t >> 6][lane] = (rv >= n) ? make_double2(0.0, 0.0)
-                                     : (rv == o) ? make_double2(1.0, 0.0) : cmul(raw, sc);
-    }
-    __syncthreads();
-    cplx y = make_double2(0.0, 0.0);
-    const cplx vi = vbuf[0][lane];
-    cplx s8[8];
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-      y = cadd(y, cmul(av[cc], vbuf[1][wq * 8 + cc]));
-      s8[cc] = cmulc(av[cc], vi);
-    }
-    // next tile's loads go out before the reductions
-    const long kn = k + gridDim.x;
-    long In = I, Jn = J;
-    if (kn < noff) {
-      trd_tile_off(kn, nt, In, Jn);
-      const cplx* src = A + (o + Jn * 64 + wq * 8) * lda + std::min(o + In * 64 + lane, n1);
-#pragma unroll
-      for (int cc = 0; cc < 8; ++cc) av[cc] = src[cc * lda];
-    }
-    // column sums over the 64 lanes: butterfly halving the values held per
-    // lane (8 -> 1), then three plain exchanges
-#pragma unroll
-    for (int half = 4, m = 32; half >= 1; half >>= 1, m >>= 1) {
-      const bool upper = (lane & m) != 0;
-#pragma unroll
-      for (int q2 = 0; q2 < half; ++q2) {
-        const cplx keep = upper ? s8[q2 + half] : s8[q2];
-        const cplx send = upper ? s8[q2] : s8[q2 + half];
-        cplx got;
-        got.x = __shfl_xor(send.x, m, 64);
-        got.y = __shfl_xor(send.y, m, 64);
-        s8[q2] = cadd(keep, got);
-      }
-    }
-    cplx z = s8[0];
-#pragma unroll
-    for (int m = 4; m >= 1; m >>= 1) {
-      z.x += __shfl_xor(z.x, m, 64);
-      z.y += __shfl_xor(z.y, m, 64);
-    }
-    if ((lane & 7) == 0) {
-      const int colid = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-      P[(J * nt + I) * 64 + wq * 8 + colid] = z;
-    }
-    red[wq][lane] = y;
-    __syncthreads();
-    if (t < 64) {
-      cplx acc = red[0][t];
-#pragma unroll
-      for (int w = 1; w < 8; ++w) acc = cadd(acc, red[w][t]);
-      P[(I * nt + J) * 64 + t] = acc;
-    }
-    k = kn;
-    I = In;
-    J = Jn;
-  }
-  // diagonal tiles (Hermitian: the upper part from the stored lower triangle)
-  for (long Id = blockIdx.x; Id < nt; Id += gridDim.x) {
-    __syncthreads();
-    if (t < 64) vbuf[1][t] = trd_v(A, lda, n, c, o + Id * 64 + t, sc);
-    __syncthreads();
-    const long row = o + Id * 64 + lane;
-    cplx y = make_double2(0.0, 0.0);
-#pragma unroll 1
-    for (int cc = 0; cc < 8; ++cc) {
-      const int cl = wq * 8 + cc;
-      const long col = o + Id * 64 + cl;
-      cplx x = make_double2(0.0, 0.0);
-      if (row < n && col < n) {
-        if (cl < lane) x = A[col * lda + row];
-        else if (cl > lane) x = cconj(A[row * lda + col]);
-        else x = make_double2(A[col * lda + row].x, 0.0);
-      }
-      y = cadd(y, cmul(x, vbuf[1][cl]));
-    }
-    red[wq][lane] = y;
-    __syncthreads();
-    if (t < 64) {
-      cplx acc = red[0][t];
-#pragma unroll
-      for (int w = 1; w < 8; ++w) acc = cadd(acc, red[w][t]);
-      P[(Id * nt + Id) * 64 + t] = acc;
-    }
   }
 }
 
@@ -731,16 +401,8 @@ void hetrd_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
       // at least 2j workgroups: each reduces some of the 2j column-step sums
       const unsigned grid = (unsigned)std::max<long>(std::min<long>(ntiles, HEMV_WGS), 2 * j);
       if (w.prof) w.prof->begin(PROF_TRD_HEMV, 16.0 * np * (np + 1.0) * 0.5, s);
-#if HEMV_VARIANT == 3
-      hipLaunchKernelGGL(k_trd_hemv8, dim3(grid), dim3(512), 0, s, n, (const cplx*)A, lda, c, j,
-                         (const cplx*)w.tpart, nb1, w.tsum, w.scal, w.d, w.e, w.tau, w.P, nt, ntiles);
-#elif HEMV_VARIANT == 2
-      hipLaunchKernelGGL(k_trd_hemv_pipe, dim3(grid), dim3(256), 0, s, n, (const cplx*)A, lda, c, j,
-                         (const cplx*)w.tpart, nb1, w.tsum, w.scal, w.d, w.e, w.tau, w.P, nt, ntiles);
-#else
       hipLaunchKernelGGL(k_trd_hemv, dim3(grid), dim3(256), 0, s, n, (const cplx*)A, lda, c, j,
                          (const cplx*)w.tpart, nb1, w.tsum, w.scal, w.d, w.e, w.tau, w.P, nt, ntiles);
-#endif
       if (w.prof) w.prof->end(PROF_TRD_HEMV, 16.0 * np * (np + 1.0) * 0.5, s);
       hipLaunchKernelGGL(k_trd_w, dim3(nt), dim3(256), 0, s, n, (const cplx*)A, lda, w.W, ldw, i0, j, c,
                          (const cplx*)w.tsum, (const cplx*)w.P, nt, (const double*)w.scal,
@@ -1007,8 +669,12 @@ void extract_v(const cplx* A, long rs, long cs, int row0, int col0, int mrows, i
 }
 
 // Forward column-wise block reflector factor: T upper (ib x ib, row-major
-// ld 64) with H_0 ... H_{ib-1} = I - V T V^H, from S = V^H V and tau.
-__global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx* tau, cplx* T) {
+// ld 64, zero elsewhere in its 64 x 64 block) with H_0 ... H_{ib-1} =
+// I - V T V^H, from S = V^H V and tau: T[i][i] = tau_i and, for j > i,
+// T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] S[l][j]. Row i depends only on its
+// own earlier entries and on S, so thread i forms it in registers with no
+// barrier between columns (ib <= QR_NB; k_larft64 below takes up to 64).
+__global__ __launch_bounds__(64) void k_larft64(int ib, const cplx* S, const cplx* tau, cplx* T) {
   __shared__ cplx Ts[64][65];
   __shared__ cplx Ss[64][65];
   const int i = threadIdx.x;
@@ -1030,6 +696,52 @@ __global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx*
   for (int r = 0; r < 64; ++r) T[r * 64 + i] = Ts[r][i];
 }
 
+__global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx* tau, cplx* T) {
+  __shared__ cplx Ss[QR_NB][QR_NB + 1];
+  __shared__ cplx ts[QR_NB];
+  const int i = threadIdx.x;
+  {
+    // all 16 loads of this thread in flight at once
+    cplx sv[QR_NB * QR_NB / 64];
+#pragma unroll
+    for (int u = 0; u < QR_NB * QR_NB / 64; ++u) {
+      const int e = i + 64 * u, r = e / QR_NB, c = e % QR_NB;
+      sv[u] = (r < ib && c < ib) ? S[r * 64 + c] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < QR_NB * QR_NB / 64; ++u) {
+      const int e = i + 64 * u;
+      Ss[e / QR_NB][e % QR_NB] = sv[u];
+    }
+  }
+  if (i < QR_NB) ts[i] = (i < ib) ? tau[i] : make_double2(0.0, 0.0);
+  __syncthreads();
+  cplx row[QR_NB];
+#pragma unroll
+  for (int j = 0; j < QR_NB; ++j) {
+    cplx acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int l = 0; l < j; ++l)
+      if (l >= i) acc = cadd(acc, cmul(row[l], Ss[l][j]));
+    cplx v = make_double2(0.0, 0.0);
+    if (i < ib && j < ib) {
+      if (j == i) v = ts[j];
+      else if (j > i) v = cmul(cscale(ts[j], -1.0), acc);
+    }
+    row[j] = v;
+  }
+  // rows through LDS, so that the stores of one row are contiguous across lanes
+  __syncthreads();
+  if (i < QR_NB) {
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) Ss[i][c] = row[c];
+  }
+  __syncthreads();
+  for (int r = 0; r < 64; ++r)
+    T[(long)r * 64 + i] = (r < QR_NB && i < QR_NB) ? Ss[r < QR_NB ? r : 0][i < QR_NB ? i : 0]
+                                                   : make_double2(0.0, 0.0);
+}
+
 void block_reflector(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib,
                             const cplx* tau, cplx* T, LinalgWork& w, hipStream_t s) {
   const long ldv = w.vmax;
@@ -1041,7 +753,8 @@ void block_reflector(const cplx* A, long rs, long cs, int row0, int col0, int mr
   ZGemm g = zgemm_args(ib, ib, mrows, zop(w.V, ldv, 0, 1), zop(w.V, ldv, 1), w.S, 64, 0,
                        make_double2(1.0, 0.0), make_double2(0.0, 0.0));
   zgemm(g, w.gpart, w.gpart_elems, s, w.prof);
-  hipLaunchKernelGGL(k_larft, dim3(1), dim3(64), 0, s, ib, (const cplx*)w.S, tau, T);
+  if (ib <= QR_NB) hipLaunchKernelGGL(k_larft, dim3(1), dim3(64), 0, s, ib, (const cplx*)w.S, tau, T);
+  else hipLaunchKernelGGL(k_larft64, dim3(1), dim3(64), 0, s, ib, (const cplx*)w.S, tau, T);
 }
 
 // Apply (I - V op(T) V^H) to the mrows x ncols block C (element (r, c) at

@@ -853,9 +853,6 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     w.P_elems = l.P;
     w.dpart = dalloc<cplx>(h, l.dpart);
     w.tsum = dalloc<cplx>(h, 2 * TRD_NB + 2);
-    w.cnt_stride = ceil_div(z.nmax, 64) + 8;
-    w.cnt = dalloc<int>(h, w.cnt_stride + 8);
-    HIPCHK(hipMemsetAsync(w.cnt, 0, sizeof(int) * (w.cnt_stride + 8), h->stream));
     w.npart = dalloc<double>(h, l.npart);
     w.d = dalloc<double>(h, z.nmax);
     w.e = dalloc<double>(h, z.nmax);
