@@ -262,7 +262,8 @@ def xy_rate(shape: tuple[int, int], chi: int, precision: str, steps: int, seed: 
     from paper_2511_23438_amd import mpsim, workloads
     lx, ly = shape
     n = lx * ly
-    cfg = mpsim.make_xy_config(lx, ly, chi, precision=precision)
+    # no preparation at init: the random start state replaces it
+    cfg = mpsim.make_xy_config(lx, ly, chi, precision=precision, tau=0.0)
     sim = mpsim.Simulation(cfg)
     sites, centre = workloads.random_mps(lx, ly, chi, seed, dims=[2] * n)
     sim.set_state(sites, centre)
