@@ -327,6 +327,7 @@ void heev(mps_sim* h, int kg, int q, cplx* U, uint64_t seed) {
 // The Gram products run in float64 whatever the precision mode; the
 // products that form C take the mode's contraction precision.
 // Returns false (nothing done) when the shape does not qualify.
+constexpr long FACTORED_MIN = 2048;  // Gram side from which the factored form pays
 bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t seed) {
   const Plan& p = h->plan;
   const int ba = h->pos[i], bb = h->pos[i + 1];
@@ -334,7 +335,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
   if (p.dim(bb) != d || d < 4 || p.model != 0) return false;
   const long b0 = h->bond[i], b1 = h->bond[i + 1], b2 = h->bond[i + 2];
   const long kg = left ? b0 * d : (long)d * b2;
-  if (kg < MPS_EIG2_MIN) return false;
+  if (kg < FACTORED_MIN) return false;
   const long np = (long)d * (d + 1) / 2;
   if ((long)(d + np) * b1 * b1 > h->theta_elems) return false;
   hipStream_t s = h->stream;
