@@ -542,3 +542,28 @@ def test_factored_gram_reduced_precision(prec):
     a, b = sim.measure(), ora.measure()
     print(prec, "z err %.2e z2 err %.2e" % (abs(a["z"] - b["z"]), abs(a["z2"] - b["z2"])))
     assert abs(a["z"] - b["z"]) < 1e-5 and abs(a["z2"] - b["z2"]) < 1e-5
+
+
+@pytest.mark.parametrize("prec,eig_path,tol", [("c64", 0, 1e-5), ("bf16x3", 0, 1e-5), ("fp64", 2, TOL)])
+def test_xy_precision_and_eigensolver_variants(prec, eig_path, tol):
+    """XY model with reduced-precision contractions (float64 truncation) and
+    with the two-stage eigensolver forced, against the float64 oracle from a
+    symmetry-free random state (4x4, chi = 8, two steps)."""
+    from oracle.xy import XYGrid, XYMPS
+    g = XYGrid(4, 4)
+    sites, centre = workloads.random_mps(4, 4, 8, 81, dims=[2] * g.n)
+    sim = mpsim.Simulation(mpsim.make_xy_config(4, 4, 8, XY_G, XY_DT, 0.0, precision=prec,
+                                                eig_path=eig_path))
+    sim.set_state(sites, centre)
+    ora = XYMPS(g, 8, XY_G, XY_DT, 0.0)
+    ora.sites = [np.array(s_, dtype=np.complex128) for s_ in sites]
+    ora.centre = centre
+    ora.log_fidelity = 0.0
+    ora.update_log = []
+    for _ in range(2):
+        sim.step(1)
+        ora.step()
+        a, b = sim.measure(), ora.measure()
+        ef = abs(a["fidelity"] - b["fidelity"]) / b["fidelity"]
+        print(prec, eig_path, "x2 err %.2e z err %.2e F(rel) %.2e" % (abs(a["z2"] - b["x2"]), abs(a["z"] - b["z"]), ef))
+        assert abs(a["z2"] - b["x2"]) < tol and abs(a["z"] - b["z"]) < tol and ef < max(tol, 1e-10)
