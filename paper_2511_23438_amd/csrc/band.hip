@@ -222,8 +222,8 @@ __global__ __launch_bounds__(256) void k_hb2st(int n, cplx* Ab, int slot, int jl
     double beta = 0.0;
     cplx tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
     if (t == 0) reflector(x[0], xn, beta, tau, scl);
-    scl.x = __shfl(scl.x, 0, 64);
-    scl.y = __shfl(scl.y, 0, 64);
+    scl.x = wave_bcast0(scl.x);
+    scl.y = wave_bcast0(scl.y);
     if (t < HB) v[t] = (t == 0) ? make_double2(1.0, 0.0) : (t < L ? cmul(x[t], scl) : make_double2(0.0, 0.0));
     if (t == 0) {
       sc[0] = beta; sc[1] = tau.x; sc[2] = tau.y;
@@ -244,15 +244,12 @@ __global__ __launch_bounds__(256) void k_hb2st(int n, cplx* Ab, int slot, int jl
     }
     // v^H D v (real): every piece of p times conj(v_q)
     double sp = cmulc(v[q], pp).x;
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-      pp.x += __shfl_xor(pp.x, off, 64);
-      pp.y += __shfl_xor(pp.y, off, 64);
-      qq.x += __shfl_xor(qq.x, off, 64);
-      qq.y += __shfl_xor(qq.y, off, 64);
-      ww.x += __shfl_xor(ww.x, off, 64);
-      ww.y += __shfl_xor(ww.y, off, 64);
-    }
+    pp.x = oct_sum(pp.x);
+    pp.y = oct_sum(pp.y);
+    qq.x = oct_sum(qq.x);
+    qq.y = oct_sum(qq.y);
+    ww.x = oct_sum(ww.x);
+    ww.y = oct_sum(ww.y);
     if (part == 0) {
       pv[q] = pp;
       qv[q] = qq;
@@ -391,13 +388,29 @@ __device__ inline double band_hash(uint64_t seed, uint64_t a, uint64_t b) {
   return ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
 }
 
+template <int M>
+__device__ inline void argmax_step(double& best, int& bi) {
+  const double ob = lane_xch<M>(best);
+  const int oi = lane_xch<M>(bi);
+  if (ob > best || (ob == best && oi < bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+
 constexpr int WR = HB + 1;        // window rows
 constexpr int WC = 2 * HB + 1;    // window columns
 constexpr int CH = 4;             // rows staged per chunk (LDS: 4 waves per CU)
+constexpr int LRW = HB + 1;       // stored L row: HB multipliers, then the pivot offset
+constexpr int CHL = 16;           // L rows loaded ahead in the substitution-only passes
 
 // One wave per eigenvector (vector index v0 + blockIdx.x, column kq of X for
 // the kq-th largest eigenvalue). Window W[row % WR][col % WC] holds rows
 // k..k+HB and columns k..k+2HB of the partially eliminated B - lambda I.
+// The first pass factors B - lambda I and keeps U (with the transformed
+// right-hand side) and L (multipliers and pivot offset per row); later passes
+// only repeat the forward substitution with the kept L on the new
+// right-hand side, the same operations on the same values as a refactoring.
 __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q, const double* lam,
                                                   int lam_off, const double* bounds, cplx* Ubuf,
                                                   int v0, cplx* X, long ldx, uint64_t seed,
@@ -409,167 +422,217 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
   const int kq = v0 + blockIdx.x;
   if (kq >= q) return;
   const int l = threadIdx.x;
-  cplx* U = Ubuf + (long)blockIdx.x * n * URW;
+  cplx* U = Ubuf + (long)blockIdx.x * n * (URW + LRW);
+  cplx* Lr = U + (long)n * URW;
   const double lmb = lam[lam_off + q - 1 - kq];
   double epsp = DBL_EPSILON * bounds[2];
   if (epsp == 0.0) epsp = DBL_MIN;
   for (int it = 0; it < iters; ++it) {
-    // ---- forward: LU with partial pivoting, RHS carried along
-    for (int e = l; e < WR * WC; e += 64) Wn[e / WC][e % WC] = make_double2(0.0, 0.0);
-    __syncthreads();
-    // rows 0..HB: B[i, jc] for jc in [0, 2HB] (Br offset o = jc - i + HB)
-    for (int e = l; e < WR * WC; e += 64) {
-      const int i = e / WC, jc = e % WC;
-      if (i < n && jc < n) {
-        const int o = jc - i + HB;
-        if (o >= 0 && o < ABW) {
-          cplx b = Br[(long)i * ABW + o];
-          if (o == HB) b.x -= lmb;
-          Wn[i % WR][jc % WC] = b;
-        }
-      }
-    }
-    if (l < WR && l < n) {
-      if (it == 0) yv[l] = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)l), 0.0);
-      else yv[l] = X[(long)l * ldx + kq];
-    }
-    // rows entering the window in chunk kc (rows kc+WR .. kc+WR+CH-1): loaded
-    // into registers one chunk ahead, so the loads are in flight while the
-    // previous chunk's rows are eliminated; the shift by lambda is applied
-    // when they are written to LDS
-    constexpr int NPF = (CH * ABW + 63) / 64;
-    cplx pf[NPF], pfy = make_double2(0.0, 0.0);
-    auto fetch = [&](int kc) {
-#pragma unroll
-      for (int j = 0; j < NPF; ++j) {
-        const int e = l + 64 * j;
-        const long i = (long)kc + WR + e / ABW;
-        pf[j] = make_double2(0.0, 0.0);
-        if (e < CH * ABW && i < n) pf[j] = Br[i * ABW + e % ABW];
-      }
-      pfy = make_double2(0.0, 0.0);
-      if (l < CH) {
-        const long i = (long)kc + WR + l;
-        if (i < n) {
-          if (it == 0) pfy = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)i), 0.0);
-          else pfy = X[i * ldx + kq];
-        }
-      }
-    };
-    auto stage_fetched = [&](int kc) {
-#pragma unroll
-      for (int j = 0; j < NPF; ++j) {
-        const int e = l + 64 * j;
-        if (e < CH * ABW) {
-          cplx b = pf[j];
-          if (e % ABW == HB && (long)kc + WR + e / ABW < n) b.x -= lmb;
-          stage[e / ABW][e % ABW] = b;
-        }
-      }
-      if (l < CH) stage[l][ABW] = pfy;
-    };
-    fetch(0);
-    __syncthreads();
-    stage_fetched(0);
-    __syncthreads();
-    for (int k0 = 0; k0 < n; k0 += CH) {
-      const bool more = k0 + CH < n;
-      if (more) fetch(k0 + CH);
-      const int kend = min(n, k0 + CH);
-      for (int k = k0; k < kend; ++k) {
-        const int cs = k % WC;
-        // pivot: largest |W[i][k]| over rows k..min(n-1, k+HB)
-        double best = -1.0;
-        int bi = k;
-        if (l < WR && k + l < n) {
-          best = cabs2(Wn[(k + l) % WR][cs]);
-          bi = k + l;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ob = __shfl_xor(best, off, 64);
-          const int oi = __shfl_xor(bi, off, 64);
-          if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
+    if (it == 0) {
+      // ---- forward: LU with partial pivoting, RHS carried along
+      for (int e = l; e < WR * WC; e += 64) Wn[e / WC][e % WC] = make_double2(0.0, 0.0);
+      __syncthreads();
+      // rows 0..HB: B[i, jc] for jc in [0, 2HB] (Br offset o = jc - i + HB)
+      for (int e = l; e < WR * WC; e += 64) {
+        const int i = e / WC, jc = e % WC;
+        if (i < n && jc < n) {
+          const int o = jc - i + HB;
+          if (o >= 0 && o < ABW) {
+            cplx b = Br[(long)i * ABW + o];
+            if (o == HB) b.x -= lmb;
+            Wn[i % WR][jc % WC] = b;
           }
         }
-        const int ks = k % WR;
-        if (bi != k) {
-          const int ps = bi % WR;
-          for (int cc = l; cc < WC; cc += 64) {
-            const cplx a = Wn[ks][cc];
-            Wn[ks][cc] = Wn[ps][cc];
-            Wn[ps][cc] = a;
-          }
-          if (l == 0) {
-            const cplx a = yv[ks];
-            yv[ks] = yv[ps];
-            yv[ps] = a;
+      }
+      if (l < WR && l < n) {
+        if (it == 0) yv[l] = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)l), 0.0);
+        else yv[l] = X[(long)l * ldx + kq];
+      }
+      // rows entering the window in chunk kc (rows kc+WR .. kc+WR+CH-1): loaded
+      // into registers one chunk ahead, so the loads are in flight while the
+      // previous chunk's rows are eliminated; the shift by lambda is applied
+      // when they are written to LDS
+      constexpr int NPF = (CH * ABW + 63) / 64;
+      cplx pf[NPF], pfy = make_double2(0.0, 0.0);
+      auto fetch = [&](int kc) {
+  #pragma unroll
+        for (int j = 0; j < NPF; ++j) {
+          const int e = l + 64 * j;
+          const long i = (long)kc + WR + e / ABW;
+          pf[j] = make_double2(0.0, 0.0);
+          if (e < CH * ABW && i < n) pf[j] = Br[i * ABW + e % ABW];
+        }
+        pfy = make_double2(0.0, 0.0);
+        if (l < CH) {
+          const long i = (long)kc + WR + l;
+          if (i < n) {
+            if (it == 0) pfy = make_double2(band_hash(seed, (uint64_t)kq, (uint64_t)i), 0.0);
+            else pfy = X[i * ldx + kq];
           }
         }
-        __syncthreads();
-        cplx ukk = Wn[ks][cs];
-        if (cabs2(ukk) < epsp * epsp) ukk = make_double2(ukk.x < 0.0 ? -epsp : epsp, 0.0);
-        const cplx yk = yv[ks];
-        // U row k: offsets 0..2HB, then the eliminated RHS value
-        for (int o = l; o < WC; o += 64) U[(long)k * URW + o] = (o == 0) ? ukk : Wn[ks][(k + o) % WC];
-        if (l == 0) U[(long)k * URW + WC] = yk;
-        // multipliers of rows k+1..k+HB
-        if (l < HB) {
-          const int i = k + 1 + l;
-          cplx li = make_double2(0.0, 0.0);
-          if (i < n) li = cmul(Wn[i % WR][cs], cinv(ukk));
-          lb[l] = li;
-          if (i < n) yv[i % WR] = csub(yv[i % WR], cmul(li, yk));
+      };
+      auto stage_fetched = [&](int kc) {
+  #pragma unroll
+        for (int j = 0; j < NPF; ++j) {
+          const int e = l + 64 * j;
+          if (e < CH * ABW) {
+            cplx b = pf[j];
+            if (e % ABW == HB && (long)kc + WR + e / ABW < n) b.x -= lmb;
+            stage[e / ABW][e % ABW] = b;
+          }
         }
-        __syncthreads();
-        {
-          // lane l updates column k+1+l of rows k+1..k+HB, eight rows at a
-          // time: all reads of a group, then all writes (rows past n hold
-          // zeros and zero multipliers, so they are updated harmlessly)
-          const int cl = (k + 1 + l) % WC;
-          const cplx u = Wn[ks][cl];
-          int slot = (k + 1) % WR;
-#pragma unroll
-          for (int g8 = 0; g8 < HB / 8; ++g8) {
-            cplx wv[8], lv[8];
-            int sl[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              sl[q] = slot;
-              slot = (slot + 1 == WR) ? 0 : slot + 1;
-              lv[q] = lb[g8 * 8 + q];
-              wv[q] = Wn[sl[q]][cl];
+        if (l < CH) stage[l][ABW] = pfy;
+      };
+      fetch(0);
+      __syncthreads();
+      stage_fetched(0);
+      __syncthreads();
+      for (int k0 = 0; k0 < n; k0 += CH) {
+        const bool more = k0 + CH < n;
+        if (more) fetch(k0 + CH);
+        const int kend = min(n, k0 + CH);
+        for (int k = k0; k < kend; ++k) {
+          const int cs = k % WC;
+          // pivot: largest |W[i][k]| over rows k..min(n-1, k+HB)
+          double best = -1.0;
+          int bi = k;
+          if (l < WR && k + l < n) {
+            best = cabs2(Wn[(k + l) % WR][cs]);
+            bi = k + l;
+          }
+          // (largest |W|^2, then lowest row): the same in every lane whatever
+          // the exchange order
+          argmax_step<1>(best, bi);
+          argmax_step<2>(best, bi);
+          argmax_step<4>(best, bi);
+          argmax_step<8>(best, bi);
+          argmax_step<16>(best, bi);
+          argmax_step<32>(best, bi);
+          const int ks = k % WR;
+          if (bi != k) {
+            const int ps = bi % WR;
+            for (int cc = l; cc < WC; cc += 64) {
+              const cplx a = Wn[ks][cc];
+              Wn[ks][cc] = Wn[ps][cc];
+              Wn[ps][cc] = a;
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) Wn[sl[q]][cl] = csub(wv[q], cmul(lv[q], u));
-          }
-        }
-        __syncthreads();
-        // advance: row k+WR takes row k's slot, column k+WC takes column k's
-        {
-          const int ni = k + WR;
-          const int rr = ni - (k0 + WR);   // its index in the staged chunk
-          for (int cc = l; cc < WC; cc += 64) {
-            // column index of slot cc in the new window [k+1, k+WC]
-            const int jc = k + 1 + ((cc - (k + 1) % WC) + WC) % WC;
-            cplx b = make_double2(0.0, 0.0);
-            if (ni < n) {
-              const int o = jc - ni + HB;
-              if (o >= 0 && o < ABW) b = stage[rr][o];
+            if (l == 0) {
+              const cplx a = yv[ks];
+              yv[ks] = yv[ps];
+              yv[ps] = a;
             }
-            Wn[ks][cc] = b;
           }
-          // the entering column is zero in every other row
-          for (int i2 = l; i2 < WR; i2 += 64)
-            if (i2 != ks) Wn[i2][cs] = make_double2(0.0, 0.0);
-          if (l == 0) yv[ks] = (ni < n) ? stage[rr][ABW] : make_double2(0.0, 0.0);
+          __syncthreads();
+          cplx ukk = Wn[ks][cs];
+          if (cabs2(ukk) < epsp * epsp) ukk = make_double2(ukk.x < 0.0 ? -epsp : epsp, 0.0);
+          const cplx yk = yv[ks];
+          // U row k: offsets 0..2HB, then the eliminated RHS value
+          for (int o = l; o < WC; o += 64) U[(long)k * URW + o] = (o == 0) ? ukk : Wn[ks][(k + o) % WC];
+          if (l == 0) U[(long)k * URW + WC] = yk;
+          // multipliers of rows k+1..k+HB (kept with the pivot offset)
+          if (l < HB) {
+            const int i = k + 1 + l;
+            cplx li = make_double2(0.0, 0.0);
+            if (i < n) li = cmul(Wn[i % WR][cs], cinv(ukk));
+            lb[l] = li;
+            Lr[(long)k * LRW + l] = li;
+            if (i < n) yv[i % WR] = csub(yv[i % WR], cmul(li, yk));
+          }
+          if (l == HB) Lr[(long)k * LRW + HB] = make_double2((double)(bi - k), 0.0);
+          __syncthreads();
+          {
+            // lane l updates column k+1+l of rows k+1..k+HB, eight rows at a
+            // time: all reads of a group, then all writes (rows past n hold
+            // zeros and zero multipliers, so they are updated harmlessly)
+            const int cl = (k + 1 + l) % WC;
+            const cplx u = Wn[ks][cl];
+            int slot = (k + 1) % WR;
+  #pragma unroll
+            for (int g8 = 0; g8 < HB / 8; ++g8) {
+              cplx wv[8], lv[8];
+              int sl[8];
+  #pragma unroll
+              for (int q = 0; q < 8; ++q) {
+                sl[q] = slot;
+                slot = (slot + 1 == WR) ? 0 : slot + 1;
+                lv[q] = lb[g8 * 8 + q];
+                wv[q] = Wn[sl[q]][cl];
+              }
+  #pragma unroll
+              for (int q = 0; q < 8; ++q) Wn[sl[q]][cl] = csub(wv[q], cmul(lv[q], u));
+            }
+          }
+          __syncthreads();
+          // advance: row k+WR takes row k's slot, column k+WC takes column k's
+          {
+            const int ni = k + WR;
+            const int rr = ni - (k0 + WR);   // its index in the staged chunk
+            for (int cc = l; cc < WC; cc += 64) {
+              // column index of slot cc in the new window [k+1, k+WC]
+              const int jc = k + 1 + ((cc - (k + 1) % WC) + WC) % WC;
+              cplx b = make_double2(0.0, 0.0);
+              if (ni < n) {
+                const int o = jc - ni + HB;
+                if (o >= 0 && o < ABW) b = stage[rr][o];
+              }
+              Wn[ks][cc] = b;
+            }
+            // the entering column is zero in every other row
+            for (int i2 = l; i2 < WR; i2 += 64)
+              if (i2 != ks) Wn[i2][cs] = make_double2(0.0, 0.0);
+            if (l == 0) yv[ks] = (ni < n) ? stage[rr][ABW] : make_double2(0.0, 0.0);
+          }
+          __syncthreads();
         }
-        __syncthreads();
+        if (more) {
+          stage_fetched(k0 + CH);
+          __syncthreads();
+        }
       }
-      if (more) {
-        stage_fetched(k0 + CH);
-        __syncthreads();
+    } else {
+      // ---- forward substitution with the kept L on the right-hand side X
+      if (l < WR && l < n) yv[l] = X[(long)l * ldx + kq];
+      // lane l < LRW holds entry l of the chunk's L rows; lane j < CHL the
+      // right-hand side of row k0 + WR + j, which enters after row k0 + j
+      cplx lc[CHL], ln[CHL], xc, xn;
+      auto fetch_l = [&](int k0, cplx (&dst)[CHL], cplx& xv) {
+#pragma unroll
+        for (int j = 0; j < CHL; ++j)
+          dst[j] = (l < LRW && k0 + j < n) ? Lr[(long)(k0 + j) * LRW + l] : make_double2(0.0, 0.0);
+        const long ie = (long)k0 + WR + l;
+        xv = (l < CHL && ie < n) ? X[ie * ldx + kq] : make_double2(0.0, 0.0);
+      };
+      fetch_l(0, lc, xc);
+      __syncthreads();
+      for (int k0 = 0; k0 < n; k0 += CHL) {
+        if (k0 + CHL < n) fetch_l(k0 + CHL, ln, xn);
+#pragma unroll
+        for (int j = 0; j < CHL; ++j) {
+          const int k = k0 + j;
+          if (k < n) {
+            const int ks = k % WR;
+            const int po = (int)wave_readlane(lc[j].x, HB);
+            if (po != 0 && l == 0) {
+              const int ps = (k + po) % WR;
+              const cplx a = yv[ks];
+              yv[ks] = yv[ps];
+              yv[ps] = a;
+            }
+            __syncthreads();
+            const cplx yk = yv[ks];
+            if (l == 0) U[(long)k * URW + WC] = yk;
+            if (l < HB && k + 1 + l < n) {
+              const int is = (k + 1 + l) % WR;
+              yv[is] = csub(yv[is], cmul(lc[j], yk));
+            }
+            __syncthreads();
+            if (l == j) yv[ks] = xc;
+            __syncthreads();
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < CHL; ++j) lc[j] = ln[j];
+        xc = xn;
       }
     }
     // ---- back substitution: lane l holds x[jc] for the jc = l (mod 64) in
@@ -618,7 +681,7 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
       __syncthreads();
     }
     // normalise (the scale first, against overflow)
-    mx = __shfl(mx, 0, 64);
+    mx = wave_bcast0(mx);
     if (!(mx > 0.0) || !isfinite(mx)) mx = 1.0;
     double s2 = 0.0;
     for (int i = l; i < n; i += 64) {
@@ -640,7 +703,7 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
 // vectors per inverse-iteration launch (bounds the U workspace)
 int band_invit_batch(int q) { return std::min(q, 1024); }
 
-long band_invit_work_elems(long n, int q) { return (long)band_invit_batch(q) * n * URW; }
+long band_invit_work_elems(long n, int q) { return (long)band_invit_batch(q) * n * (URW + LRW); }
 
 void band_invit(int n, const cplx* Br, int q, int lam_off, LinalgWork& w, cplx* X, long ldx,
                 uint64_t seed, hipStream_t s) {

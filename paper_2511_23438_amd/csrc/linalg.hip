@@ -23,12 +23,6 @@
 
 namespace mpsim {
 
-__device__ inline cplx wave_csum(cplx v) {
-  v.x = wave_sum(v.x);
-  v.y = wave_sum(v.y);
-  return v;
-}
-
 static ZOp strided_op(const cplx* base, long rs, long cs, int conj = 0) {
   if (cs == 1) return zop(base, rs, 0, conj);
   return zop(base, cs, 1, conj);
@@ -448,10 +442,11 @@ __global__ __launch_bounds__(256) void k_trd_prep(int n, const double* d, const 
       emax = fmax(emax, e[i] * e[i]);
     }
   }
+#pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, off, 64));
-    hi = fmax(hi, __shfl_xor(hi, off, 64));
-    emax = fmax(emax, __shfl_xor(emax, off, 64));
+    lo = fmin(lo, lane_xch_bit(lo, off));
+    hi = fmax(hi, lane_xch_bit(hi, off));
+    emax = fmax(emax, lane_xch_bit(emax, off));
   }
   __shared__ double slo[4], shi[4], sem[4];
   int w = threadIdx.x >> 6;
@@ -789,8 +784,9 @@ void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, int tcon
 // applied to the reduced sums, so the dot products v^H A[:,jj] need no second
 // pass. The step then applies the reflector to its rows and forms the
 // partial sums of column c+1 from the updated values it holds.
-// Partial layout: part p = 4 * workgroup + wave; values 0..30 are the
-// products, 31 holds |x|^2.
+// Partial layout: one row of QR_NB values per workgroup (its four waves'
+// sums added in LDS first, so the next step has a quarter as many rows to
+// read); values 0..30 are the products, 31 holds |x|^2.
 
 // butterfly over the 64 lanes of 32 complex values (halving the values held
 // per lane at each exchange), then one plain exchange; lane l with (l & 1) == 0
@@ -801,8 +797,10 @@ __device__ inline cplx qr_butterfly(cplx vals[QR_NB], int lane, int& vid) {
     const bool upper = (lane & mm) != 0;
 #pragma unroll
     for (int q2 = 0; q2 < half; ++q2) {
-      const cplx keep = upper ? vals[q2 + half] : vals[q2];
-      const cplx send = upper ? vals[q2] : vals[q2 + half];
+      // selected by value: a conditional between two array elements takes
+      // an element's address, which would put the array in scratch memory
+      const cplx keep = csel(upper, vals[q2], vals[q2 + half]);
+      const cplx send = csel(upper, vals[q2 + half], vals[q2]);
       cplx got;
       got.x = __shfl_xor(send.x, mm, 64);
       got.y = __shfl_xor(send.y, mm, 64);
@@ -817,9 +815,21 @@ __device__ inline cplx qr_butterfly(cplx vals[QR_NB], int lane, int& vid) {
   return z;
 }
 
+// Each wave's butterfly result (lanes with (lane & 1) == 0 hold value vid)
+// is added over the four waves in a fixed order; the workgroup writes its row
+// of partials. Every thread must call it.
+__device__ inline void qr_store_partials(cplx z, int vid, cplx (*wred)[QR_NB], cplx* part) {
+  const int t = threadIdx.x;
+  if ((t & 1) == 0) wred[t >> 6][vid] = z;
+  __syncthreads();
+  if (t < QR_NB)
+    part[(long)blockIdx.x * QR_NB + t] = cadd(cadd(wred[0][t], wred[1][t]), cadd(wred[2][t], wred[3][t]));
+}
+
 // partial sums of the first column c of a panel (rows c+1 .. m-1)
 __global__ __launch_bounds__(256) void k_qr_first(int m, const cplx* A, long rs, long cs, int c,
                                                   int pe, cplx* piv, cplx* part) {
+  __shared__ cplx wred[4][QR_NB];
   const int t = threadIdx.x, lane = t & 63;
   // copy of the pivot row c (columns c .. pe-1) for the first column step
   if (blockIdx.x == 0 && t < QR_NB)
@@ -836,7 +846,7 @@ __global__ __launch_bounds__(256) void k_qr_first(int m, const cplx* A, long rs,
   vals[QR_NB - 1] = make_double2(cabs2(x), 0.0);
   int vid;
   const cplx z = qr_butterfly(vals, lane, vid);
-  if ((lane & 1) == 0) part[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + vid] = z;
+  qr_store_partials(z, vid, wred, part);
 }
 
 // The pivot row c is read from piv, a copy written by the previous launch:
@@ -934,7 +944,8 @@ __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs
   vals[QR_NB - 1] = make_double2(cabs2(x), 0.0);
   int vid;
   const cplx z = qr_butterfly(vals, lane, vid);
-  if ((lane & 1) == 0) part_next[((long)blockIdx.x * 4 + (t >> 6)) * QR_NB + vid] = z;
+  // red is free again: its last reader (wj) is behind a barrier
+  qr_store_partials(z, vid, red, part_next);
 }
 
 void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream_t s) {
@@ -950,14 +961,14 @@ void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream
     const int nb0 = std::max(1, ceil_div(m - p0 - 1, 256));
     hipLaunchKernelGGL(k_qr_first, dim3(nb0), dim3(256), 0, s, m, (const cplx*)A, rs, cs, p0, pe, pivA,
                        partA);
-    int nparts = nb0 * 4;
+    int nparts = nb0;
     for (int c = p0; c < pe; ++c) {
       const int nbr = ceil_div(m - c, 256);
       hipLaunchKernelGGL(k_qr_col, dim3(nbr), dim3(256), 0, s, m, A, rs, cs, c, pe, (const cplx*)pivA,
                          (const cplx*)partA, nparts, pivB, partB, w.qtau);
       std::swap(pivA, pivB);
       std::swap(partA, partB);
-      nparts = nbr * 4;
+      nparts = nbr;
     }
     const int ib = pe - p0;
     cplx* T = w.T + (long)panel * 4096;

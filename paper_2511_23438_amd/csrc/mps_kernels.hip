@@ -16,11 +16,15 @@ __global__ __launch_bounds__(256) void k_apply_u1(cplx* site, int b0, int d, int
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < pairs;
        idx += (long)gridDim.x * blockDim.x) {
     const long a = idx / b1, c = idx % b1;
+    // fully unrolled over the largest d, so v stays in registers
     cplx v[16];
-    for (int t = 0; t < d; ++t) v[t] = site[(a * d + t) * b1 + c];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = (t < d) ? site[(a * d + t) * b1 + c] : make_double2(0.0, 0.0);
     for (int s = 0; s < d; ++s) {
       cplx acc = make_double2(0.0, 0.0);
-      for (int t = 0; t < d; ++t) acc = cadd(acc, cmul(Us[s * d + t], v[t]));
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (t < d) acc = cadd(acc, cmul(Us[s * d + t], v[t]));
       site[(a * d + s) * b1 + c] = acc;
     }
   }
