@@ -753,6 +753,20 @@ __global__ void zgemm_reduce(ZGemmDev gd) {
   }
 }
 
+// The same product as its transpose: C^T = op(B)^T op(A)^T, with the result
+// stored in the other orientation.
+static void transpose_problem(ZGemm& g) {
+  std::swap(g.A, g.B);
+  g.A.trans ^= 1;
+  g.B.trans ^= 1;
+  std::swap(g.A2, g.B2);
+  g.A2.trans ^= 1;
+  g.B2.trans ^= 1;
+  std::swap(g.M, g.N);
+  g.transC ^= 1;
+  std::swap(g.lower_only, g.upper_only);
+}
+
 void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Prof* prof) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return;
   ZGemm g = g0;
@@ -763,19 +777,16 @@ void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Pr
     g.transC = 0;
     g.K = g.M;
   }
-  if (g.transC && g.epi == EPI_STORE) {
-    // A column-major result is stored as C^T = op(B)^T op(A)^T, row-major,
-    // so that neighbouring lanes write neighbouring addresses.
-    std::swap(g.A, g.B);
-    g.A.trans ^= 1;
-    g.B.trans ^= 1;
-    std::swap(g.A2, g.B2);
-    g.A2.trans ^= 1;
-    g.B2.trans ^= 1;
-    std::swap(g.M, g.N);
-    g.transC = 0;
-    std::swap(g.lower_only, g.upper_only);
-  }
+  // A column-major result is stored as C^T, row-major, so that neighbouring
+  // lanes write neighbouring addresses.
+  if (g.transC && g.epi == EPI_STORE) transpose_problem(g);
+  // A float64 result at most 32 rows high and wider than 32 is formed as its
+  // transpose, whose at most 32 columns take the narrow wave layout (no MFMA
+  // work on the empty half of each 64 x 64 tile); it is stored back through
+  // transC.
+  if (!g.herm_a && g.epi == EPI_STORE && g.prec == GEMM_F64 && !g.lower_only && !g.upper_only &&
+      g.M <= 32 && g.N > 32)
+    transpose_problem(g);
   ZGemmDev gd;
   gd.g = g;
   gd.ksplit = 1;
