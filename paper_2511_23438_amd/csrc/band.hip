@@ -148,17 +148,77 @@ void he2hb_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
   }
 }
 
-// X (n x q row-major) <- Q1 X, Q1 the product of the stage-1 panel reflectors
-// (stored below the band of A, block factors in w.T1).
+// Block factor of two consecutive panels a, b: with H_a = I - Va Ta Va^H and
+// H_b = I - Vb Tb Vb^H, H_a H_b = I - [Va Vb] T [Va Vb]^H for
+// T = [[Ta, -Ta S Tb], [0, Tb]], S = Va^H Vb (HB x kb2, row-major ld 64).
+// Ta, Tb and T are row-major in 64 x 64 blocks; T is zero past HB + kb2.
+__global__ __launch_bounds__(256) void k_pair_t(const cplx* Ta, const cplx* Tb, const cplx* S, int kb2,
+                                                cplx* T) {
+  __shared__ cplx ta[HB][HB + 1], tb[HB][HB + 1], sm[HB][HB + 1], y[HB][HB + 1];
+  const int t = threadIdx.x;
+  const cplx zero = make_double2(0.0, 0.0);
+  for (int e = t; e < HB * HB; e += 256) {
+    const int i = e / HB, j = e % HB;
+    ta[i][j] = Ta[i * 64 + j];
+    tb[i][j] = (i < kb2 && j < kb2) ? Tb[i * 64 + j] : zero;
+    sm[i][j] = (j < kb2) ? S[i * 64 + j] : zero;
+  }
+  __syncthreads();
+  for (int e = t; e < HB * HB; e += 256) {
+    const int i = e / HB, j = e % HB;
+    cplx acc = zero;
+    for (int l = 0; l < HB; ++l) acc = cadd(acc, cmul(ta[i][l], sm[l][j]));
+    y[i][j] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int i = e / 64, j = e % 64;
+    cplx v = zero;
+    if (i < HB && j < HB) {
+      v = ta[i][j];
+    } else if (i < HB) {
+      cplx acc = zero;
+      for (int l = 0; l < HB; ++l) acc = cadd(acc, cmul(y[i][l], tb[l][j - HB]));
+      v = make_double2(-acc.x, -acc.y);
+    } else if (j >= HB) {
+      v = tb[i - HB][j - HB];
+    }
+    T[i * 64 + j] = v;
+  }
+}
+
+// X (n x q row-major) <- Q1 X, Q1 = H_0 H_1 ... the product of the stage-1
+// panel reflectors (stored below the band of A, block factors in w.T1).
+// Panels are applied two at a time (the last one alone when their number is
+// odd): the reflectors of panels a and a + 1 form one unit lower trapezoidal
+// block of up to 2 HB columns from row a HB + HB, so X is read and written
+// once per pair.
 void he2hb_backtransform(int n, const cplx* A, long lda, int q, cplx* X, long ldx, LinalgWork& w,
                          hipStream_t s) {
+  const cplx one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
   int np = 0;
   for (int i0 = 0; i0 + HB < n - 1; i0 += HB) ++np;
-  for (int p = np - 1; p >= 0; --p) {
+  int p = np - 1;
+  if (np % 2 == 1) {
     const int i0 = p * HB, o = i0 + HB, m = n - o;
     const int kb = std::min(HB, m);
     extract_v(A, 1, lda, o, i0, m, kb, w.V, w.vmax, s);
     apply_block_reflector(m, q, kb, w.T1 + (long)p * 4096, 0, X + (long)o * ldx, ldx, 1, w, s);
+    --p;
+  }
+  for (; p >= 1; p -= 2) {
+    const int a = p - 1;
+    const int i0 = a * HB, o = i0 + HB, m = n - o;
+    const int kb2 = std::min(HB, m - HB);
+    const int ib = HB + kb2;
+    extract_v(A, 1, lda, o, i0, m, ib, w.V, w.vmax, s);
+    // S = Va^H Vb (HB x kb2, ld 64)
+    ZGemm gs = zgemm_args(HB, kb2, m, zop(w.V, w.vmax, 0, 1), zop(w.V + (long)HB * w.vmax, w.vmax, 1),
+                          w.S, 64, 0, one, zero);
+    zgemm(gs, w.gpart, w.gpart_elems, s, w.prof);
+    hipLaunchKernelGGL(k_pair_t, dim3(1), dim3(256), 0, s, (const cplx*)(w.T1 + (long)a * 4096),
+                       (const cplx*)(w.T1 + (long)(a + 1) * 4096), (const cplx*)w.S, kb2, w.T);
+    apply_block_reflector(m, q, ib, w.T, 0, X + (long)o * ldx, ldx, 1, w, s);
   }
 }
 
