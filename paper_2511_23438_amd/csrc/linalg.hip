@@ -468,12 +468,32 @@ __global__ __launch_bounds__(256) void k_trd_prep(int n, const double* d, const 
   }
 }
 
+// Number of eigenvalues of the tridiagonal (d, e2 = e^2) below x. The
+// entries are read in blocks of SC (the same addresses in every lane, so the
+// loads of a block are issued together and only the first waits), then the
+// recurrence runs through the block; the arithmetic is that of a plain loop.
+constexpr int SC = 16;
 __device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) <= pivmin) q = -pivmin;
   if (q < 0.0) ++cnt;
-  for (int i = 1; i < n; ++i) {
+  int i = 1;
+  for (; i + SC <= n; i += SC) {
+    double dd[SC], ee[SC];
+#pragma unroll
+    for (int u = 0; u < SC; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < SC; ++u) {
+      q = dd[u] - x - ee[u] / q;
+      if (fabs(q) <= pivmin) q = -pivmin;
+      if (q < 0.0) ++cnt;
+    }
+  }
+  for (; i < n; ++i) {
     q = d[i] - x - e2[i - 1] / q;
     if (fabs(q) <= pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
