@@ -104,12 +104,13 @@ void he2hb_lower(int n, cplx* A, long lda, LinalgWork& w, hipStream_t s) {
       zgemm(gx, w.gpart, w.gpart_elems, s, w.prof);
       if (ka > 0) {
         const long r0 = o - base;
-        ZGemm gpw = zgemm_args(ka, kb, m, zop(Wg + r0, ld, 0, 1), zop(V, ld, 1), Pw, HB, 0, one,
-                               zero);
-        zgemm(gpw, w.gpart, w.gpart_elems, s, w.prof);
-        ZGemm gpv = zgemm_args(ka, kb, m, zop(Vg + r0, ld, 0, 1), zop(V, ld, 1), Pv, HB, 0, one,
-                               zero);
-        zgemm(gpv, w.gpart, w.gpart_elems, s, w.prof);
+        // Pw = Wg^H V and Pv = Vg^H V as one batch of two (same V)
+        ZGemm gp = zgemm_args(ka, kb, m, zop(Wg + r0, ld, 0, 1), zop(V, ld, 1), Pw, HB, 0, one,
+                              zero);
+        gp.batch = 2;
+        gp.A.stride = (long)(Vg - Wg);
+        gp.strideC = (long)(Pv - Pw);
+        zgemm(gp, w.gpart, w.gpart_elems, s, w.prof);
         ZGemm gxc = zgemm_args(m, kb, 2 * ka, zop(Vg + r0, ld, 1), zop(Pw, HB, 0), w.X2, 64, 0, mone,
                                one);
         gxc.kcat = ka;

@@ -588,24 +588,44 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double* d, const doub
     }
   }
   AT(fd, n - 1) = di;
-  for (int i = 0; i < n; ++i) {
-    const double v = AT(fd, i);
-    if (fabs(v) < epsp) AT(fd, i) = (v < 0.0) ? -epsp : epsp;
+  // The passes below read each chunk of IC rows into registers before any of
+  // the chunk's stores (AT addresses depend on q, so the compiler cannot
+  // move a load above an earlier store itself); every row is read before it
+  // is written, and the arithmetic is that of the plain loops.
+  constexpr int IC = 16;
+  for (int i0 = 0; i0 < n; i0 += IC) {
+    double v[IC];
+#pragma unroll
+    for (int u = 0; u < IC; ++u)
+      if (i0 + u < n) v[u] = AT(fd, i0 + u);
+#pragma unroll
+    for (int u = 0; u < IC; ++u)
+      if (i0 + u < n && fabs(v[u]) < epsp) AT(fd, i0 + u) = (v[u] < 0.0) ? -epsp : epsp;
   }
   for (int i = 0; i < n; ++i) AT(xx, i) = hash_uniform(seed, (uint64_t)kq, (uint64_t)i);
   for (int it = 0; it < 3; ++it) {
     // forward: apply the row interchanges and multipliers
     double cur = AT(xx, 0);
-#pragma unroll 8
-    for (int i = 0; i < n - 1; ++i) {
-      const double nxt = AT(xx, i + 1);
-      if (AT(pv, i) == 0.0) {
-        AT(xx, i) = cur;
-        cur = nxt - AT(fl, i) * cur;
-      } else {
-        AT(xx, i) = nxt;
-        cur = cur - AT(fl, i) * nxt;
-      }
+    for (int i0 = 0; i0 < n - 1; i0 += IC) {
+      double nx[IC], fv[IC], pw[IC];
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i0 + u < n - 1) {
+          nx[u] = AT(xx, i0 + u + 1);
+          fv[u] = AT(fl, i0 + u);
+          pw[u] = AT(pv, i0 + u);
+        }
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i0 + u < n - 1) {
+          if (pw[u] == 0.0) {
+            AT(xx, i0 + u) = cur;
+            cur = nx[u] - fv[u] * cur;
+          } else {
+            AT(xx, i0 + u) = nx[u];
+            cur = cur - fv[u] * nx[u];
+          }
+        }
     }
     AT(xx, n - 1) = cur;
     // backward: upper triangular with two superdiagonals
@@ -619,26 +639,62 @@ __global__ __launch_bounds__(64) void k_invit(int n, const double* d, const doub
       x1 = v;
     }
     double mx = fmax(fabs(x1), fabs(x2));
-#pragma unroll 8
-    for (int i = n - 3; i >= 0; --i) {
-      const double v = (AT(xx, i) - AT(fu, i) * x1 - AT(fu2, i) * x2) / AT(fd, i);
-      AT(xx, i) = v;
-      x2 = x1;
-      x1 = v;
-      mx = fmax(mx, fabs(v));
+    for (int i1 = n - 3; i1 >= 0; i1 -= IC) {
+      double xv[IC], uv[IC], u2[IC], dv[IC];
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i1 - u >= 0) {
+          xv[u] = AT(xx, i1 - u);
+          uv[u] = AT(fu, i1 - u);
+          u2[u] = AT(fu2, i1 - u);
+          dv[u] = AT(fd, i1 - u);
+        }
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i1 - u >= 0) {
+          const double v = (xv[u] - uv[u] * x1 - u2[u] * x2) / dv[u];
+          AT(xx, i1 - u) = v;
+          x2 = x1;
+          x1 = v;
+          mx = fmax(mx, fabs(v));
+        }
     }
     if (!(mx > 0.0) || !isfinite(mx)) mx = 1.0;
     double s2 = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double v = AT(xx, i) / mx;
-      s2 += v * v;
+    for (int i0 = 0; i0 < n; i0 += IC) {
+      double xv[IC];
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i0 + u < n) xv[u] = AT(xx, i0 + u);
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i0 + u < n) {
+          const double v = xv[u] / mx;
+          s2 += v * v;
+        }
     }
     double nrm = sqrt(s2);
     if (!(nrm > 0.0)) nrm = 1.0;
     const double sc = 1.0 / (mx * nrm);
-    for (int i = 0; i < n; ++i) AT(xx, i) = AT(xx, i) * sc;
+    for (int i0 = 0; i0 < n; i0 += IC) {
+      double xv[IC];
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i0 + u < n) xv[u] = AT(xx, i0 + u);
+#pragma unroll
+      for (int u = 0; u < IC; ++u)
+        if (i0 + u < n) AT(xx, i0 + u) = xv[u] * sc;
+    }
   }
-  for (int i = 0; i < n; ++i) X[(long)i * ldx + kq] = make_double2(AT(xx, i), 0.0);
+  for (int i0 = 0; i0 < n; i0 += IC) {
+    double xv[IC];
+#pragma unroll
+    for (int u = 0; u < IC; ++u)
+      if (i0 + u < n) xv[u] = AT(xx, i0 + u);
+#pragma unroll
+    for (int u = 0; u < IC; ++u)
+      if (i0 + u < n) X[(long)(i0 + u) * ldx + kq] = make_double2(xv[u], 0.0);
+  }
 #undef AT
 }
 
@@ -692,22 +748,35 @@ void extract_v(const cplx* A, long rs, long cs, int row0, int col0, int mrows, i
 __global__ __launch_bounds__(64) void k_larft64(int ib, const cplx* S, const cplx* tau, cplx* T) {
   __shared__ cplx Ts[64][65];
   __shared__ cplx Ss[64][65];
+  __shared__ cplx ts[64];
   const int i = threadIdx.x;
-  for (int r = 0; r < 64; ++r) {
-    Ts[r][i] = make_double2(0.0, 0.0);
-    Ss[r][i] = (r < ib && i < ib) ? S[r * 64 + i] : make_double2(0.0, 0.0);
+  ts[i] = (i < ib) ? tau[i] : make_double2(0.0, 0.0);
+  // column i of S, 16 loads in flight at a time
+  for (int r0 = 0; r0 < 64; r0 += 16) {
+    cplx sv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      sv[u] = (r0 + u < ib && i < ib) ? S[(r0 + u) * 64 + i] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      Ts[r0 + u][i] = make_double2(0.0, 0.0);
+      Ss[r0 + u][i] = sv[u];
+    }
   }
   __syncthreads();
+  // thread i reads and writes only row i of Ts (and reads Ss): no barrier
+  // between columns
   for (int j = 0; j < ib; ++j) {
-    const cplx mt = cscale(tau[j], -1.0);
-    cplx acc = make_double2(0.0, 0.0);
-    if (i < j)
+    if (i < j) {
+      cplx acc = make_double2(0.0, 0.0);
+#pragma unroll 8
       for (int l = i; l < j; ++l) acc = cadd(acc, cmul(Ts[i][l], Ss[l][j]));
-    __syncthreads();
-    if (i < j) Ts[i][j] = cmul(mt, acc);
-    if (i == j) Ts[j][j] = tau[j];
-    __syncthreads();
+      Ts[i][j] = cmul(cscale(ts[j], -1.0), acc);
+    } else if (i == j) {
+      Ts[i][i] = ts[i];
+    }
   }
+  __syncthreads();
   for (int r = 0; r < 64; ++r) T[r * 64 + i] = Ts[r][i];
 }
 
