@@ -261,11 +261,14 @@ def test_two_stage_full_bond_dimension_matches_state_vector(R, C, chi, steps):
 
 
 @pytest.mark.parametrize("R,C,chi,steps,seed", [(4, 4, 16, 3, 41), (5, 6, 64, 1, 42),
-                                                 (6, 8, 32, 1, 43), (3, 5, 24, 2, 44)])
+                                                 (6, 8, 32, 1, 43), (3, 5, 24, 2, 44),
+                                                 (4, 4, 20, 2, 46), (5, 6, 18, 1, 47)])
 def test_two_stage_truncating_parity(R, C, chi, steps, seed):
     """Two-stage eigensolver against the oracle's SVD truncation from a
     symmetry-free start state (Gram sides up to 512: several stage-1 panels
-    and bulge-chasing sweeps)."""
+    and bulge-chasing sweeps). Sides 80 (4x4, chi 20) and 144 (5x6, chi 18)
+    end the stage-1 back-transform with a pair of panels whose second panel
+    is 16 columns wide."""
     sites, centre = workloads.random_mps(R, C, chi, seed)
     sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, eig_path=2))
     sim.set_state(sites, centre)
