@@ -114,12 +114,7 @@ __device__ inline double wave_readlane(double v, int src) {
 }
 
 // Lane 0's value in every lane.
-__device__ inline double wave_bcast0(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 0);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 0);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
+__device__ inline double wave_bcast0(double v) { return wave_readlane(v, 0); }
 
 // Block-wide sum of one double (all threads get the result). `sh` needs
 // blockDim.x / 64 doubles of shared memory. Fixed reduction order.

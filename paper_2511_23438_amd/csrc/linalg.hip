@@ -743,8 +743,9 @@ void extract_v(const cplx* A, long rs, long cs, int row0, int col0, int mrows, i
 // ld 64, zero elsewhere in its 64 x 64 block) with H_0 ... H_{ib-1} =
 // I - V T V^H, from S = V^H V and tau: T[i][i] = tau_i and, for j > i,
 // T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] S[l][j]. Row i depends only on its
-// own earlier entries and on S, so thread i forms it in registers with no
-// barrier between columns (ib <= QR_NB; k_larft64 below takes up to 64).
+// own earlier entries and on S, so thread i forms it alone, with no barrier
+// between columns: k_larft64 (ib <= 64) keeps the rows in LDS, k_larft
+// (ib <= QR_NB) in registers.
 __global__ __launch_bounds__(64) void k_larft64(int ib, const cplx* S, const cplx* tau, cplx* T) {
   __shared__ cplx Ts[64][65];
   __shared__ cplx Ss[64][65];
