@@ -41,6 +41,8 @@ import os
 import sys
 import time
 
+T_PROC0 = time.perf_counter()   # the wall budget counts from here
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -173,53 +175,59 @@ def cpu_baseline(rows: int, cols: int, chi: int, budget_s: float, schedule: int 
                                                        chi))}
 
 
-def served(time_limit: float, chi_cap: int, n_req: int, seed: int = 2511) -> dict:
-    """Continuous-batching run over a seeded Poisson trace (50 requests/s,
-    grids 4x4..7x8, chi log-uniform, 10-40 steps, complex64 contractions),
-    with chi capped so the run stays bounded; admission stops after
-    `time_limit` seconds and the admitted requests run to completion."""
+def served(time_limit: float, chi_cap: int, n_req: int, hard_stop_s: float,
+           seed: int = 2511) -> dict:
+    """Continuous-batching run over the first `n_req` requests of the seeded
+    Poisson trace of the served workload (50 requests/s, grids 4x4..7x8, chi
+    log-uniform in [64, chi_cap], 10-40 steps each, complex64 contractions):
+    admission closes after `time_limit` seconds and every instance stops
+    after its current step at `hard_stop_s`; the steps completed by then
+    give the per-step latency distribution and the aggregate rate."""
     import torch
     from paper_2511_23438_amd import serve, workloads
     trace = workloads.serving_trace(n_req, seed=seed, chi_max=chi_cap)
     free, total = torch.cuda.mem_get_info()
-    srv = serve.Server(budget_bytes=int(0.5 * free), max_active=16, seed=seed)
-    out = srv.run(trace, time_limit_s=time_limit)
-    out.pop("results")
+    srv = serve.Server(budget_bytes=int(0.8 * free), max_active=16, seed=seed, depth=1)
+    out = srv.run(trace, time_limit_s=time_limit, hard_stop_s=hard_stop_s)
+    res = out.pop("results")
+    out["requests"] = [{"grid": "%dx%d" % (r.inst.rows, r.inst.cols), "chi": r.inst.chi,
+                        "steps": r.inst.steps, "steps_done": len(r.step_ms),
+                        "finished": r.finished} for r in sorted(res, key=lambda r: r.rid)]
     out.update({"requests_in_trace": n_req, "chi_cap": chi_cap, "precision": "c64",
                 "arrival_rate_per_s": 50.0})
     return out
 
 
-def concurrent(rows: int, cols: int, chi: int, precision: str, schedule: int, count: int,
-               seed: int) -> dict:
-    """`count` independent instances of the workload (distinct seeded random
-    start states at saturated bonds), each on its own stream, stepped
-    together through the batched entry point; one step and one measurement
-    per instance in the timed region."""
+def concurrent_from(sites, centre, rows: int, cols: int, chi: int, precision: str,
+                    schedule: int, count: int) -> dict:
+    """`count` independent instances of the workload, each loaded with the
+    given start state and on its own stream, stepped together through the
+    batched entry point; one step and one measurement per instance in the
+    timed region."""
     import torch
-    from paper_2511_23438_amd import mpsim, workloads
+    from paper_2511_23438_amd import mpsim
     sims, streams = [], []
-    for k in range(count):
-        st = torch.cuda.Stream()
-        cfg = mpsim.make_config(rows, cols, chi, precision=precision, schedule=schedule)
-        with torch.cuda.stream(st):
-            sim = mpsim.Simulation(cfg, stream=st.cuda_stream)
-        sites, centre = workloads.random_mps(rows, cols, chi, seed + 1 + k, centre=rows - 1)
-        sim.set_state(sites, centre)
-        del sites
-        sims.append(sim)
-        streams.append(st)
-        log("concurrent instance %d loaded" % k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mpsim.apply_batched(sims, 1)
-    obs = [s.measure() for s in sims]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    for s in sims:
-        s.free()
-    return {"instances": count, "seconds": el, "steps_per_s": count / el,
-            "per_instance_steps_per_s": 1.0 / el,
+    try:
+        for k in range(count):
+            st = torch.cuda.Stream()
+            cfg = mpsim.make_config(rows, cols, chi, precision=precision, schedule=schedule,
+                                    seed=k)
+            with torch.cuda.stream(st):
+                sim = mpsim.Simulation(cfg, stream=st.cuda_stream)
+            sims.append(sim)
+            sim.set_state(sites, centre)
+            streams.append(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mpsim.apply_batched(sims, 1)
+        obs = [s.measure() for s in sims]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        for s in sims:
+            s.free()
+    return {"instances": count, "precision": precision, "seconds": el,
+            "steps_per_s": count / el, "per_instance_steps_per_s": 1.0 / el,
             "z": [o["z"] for o in obs], "fidelity": [o["fidelity"] for o in obs]}
 
 
@@ -285,20 +293,116 @@ def xy_rate(shape: tuple[int, int], chi: int, precision: str, steps: int, seed: 
             "fidelity": obs["fidelity"]}
 
 
+def state_rate(sites, centre, rows: int, cols: int, chi: int, precision: str, schedule: int,
+               theta0: float, warmup: int, max_steps: int, deadline: float, prof: str,
+               min_work: float, reserve_fn=None) -> dict:
+    """Timed Trotter steps of one instance loaded with the given start state:
+    `warmup` untimed steps, then up to `max_steps` timed steps (each a whole
+    step plus one measurement), stopping before a step that would end after
+    `deadline` (perf_counter seconds; the first timed step always runs).
+    `reserve_fn(step_seconds)` may move the deadline earlier once the step
+    time is known. The launch class `prof` is timed with HIP events on the
+    library's stream over the timed steps."""
+    import torch
+    from paper_2511_23438_amd import mpsim
+    cfg = mpsim.make_config(rows, cols, chi, theta0=theta0, precision=precision,
+                            schedule=schedule)
+    sim = mpsim.Simulation(cfg)
+    try:
+        sim.set_state(sites, centre)
+        est = None
+        done_w = 0
+        for w in range(warmup):
+            if est is not None and time.perf_counter() + 2 * est > deadline:
+                break
+            t0 = time.perf_counter()
+            sim.step(1)
+            sim.measure()
+            est = time.perf_counter() - t0
+            done_w += 1
+            log("[%s] warmup step %d: %.2fs" % (precision, w + 1, est))
+            if reserve_fn is not None:
+                deadline = min(deadline, reserve_fn(est))
+        t_start = [time.perf_counter()]
+
+        def progress(step, upd, n):
+            if upd % 6 == 0 or upd == n:
+                log("  [%s] update %d/%d enqueued, %.1fs" % (precision, upd, n,
+                                                            time.perf_counter() - t_start[0]))
+        sim.set_progress(progress)
+        sim.profile(prof, min_work=min_work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_start[0] = t0
+        k = 0
+        obs = None
+        while k < max_steps:
+            if k > 0:
+                per = (time.perf_counter() - t0) / k
+                if time.perf_counter() + per > deadline:
+                    break
+            sim.step(1)
+            obs = sim.measure()          # part of the step: one measurement per step
+            k += 1
+            log("[%s] step %d: %.2fs since start, <Z>=%.6f <Z^2>=%.6f F=%.4e" % (
+                precision, k, time.perf_counter() - t0, obs["z"], obs["z2"], obs["fidelity"]))
+            if k == 1 and reserve_fn is not None:
+                deadline = min(deadline, reserve_fn(time.perf_counter() - t0))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ms_k, launches, work = sim.profile_read()
+        sim.profile("off")
+        sim.set_progress(None)
+        return {"precision": precision, "steps": k, "warmup": done_w, "seconds": elapsed,
+                "steps_per_s": k / elapsed, "ms_per_step": 1e3 * elapsed / k,
+                "prof": {"kernel": prof, "ms": ms_k, "launches": launches, "work": work},
+                "observables": {"z": obs["z"], "z2": obs["z2"], "fidelity": obs["fidelity"],
+                                "norm": obs["norm"]}}
+    finally:
+        sim.free()
+
+
+def roofline(prof: dict, elapsed: float) -> dict:
+    bound = DOMINANT[prof["kernel"]]
+    peak, unit = PEAK[bound]
+    launches = max(prof["launches"], 1)
+    avg_s = (prof["ms"] / 1e3) / launches
+    per_launch = prof["work"] / launches
+    scale = 1e9 if bound == "hbm" else 1e12
+    achieved = per_launch / avg_s / scale if avg_s > 0 else 0.0
+    return {"bound": "hbm" if bound == "hbm" else "mfma", "achieved": achieved, "peak": peak,
+            "unit": unit, "frac": achieved / peak, "traffic": None,
+            "kernel": prof["kernel"], "launches": prof["launches"],
+            "avg_launch_us": avg_s * 1e6, "work_per_launch": per_launch,
+            "kernel_time_share": (prof["ms"] / 1e3) / elapsed if elapsed > 0 else 0.0}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps requested (fewer are timed if the wall budget ends first)")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed steps requested; at most one is run from the saturated "
+                         "random start state, whose steps already have steady-state shapes")
+    ap.add_argument("--budget", type=float, default=480.0,
+                    help="wall-clock seconds from process start to the JSON line; the timed "
+                         "loop and the later legs are cut to fit")
     ap.add_argument("--start", default="random", choices=["random", "product"])
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--pmc-sample", action="store_true",
                     help="counter sample: a 1 GiB elementwise kernel, then one bulk two-site "
                          "update with SWAP (direct Gram matrix)")
+    ap.add_argument("--pmc-eig-path", type=int, default=0, choices=[0, 1, 2],
+                    help="eigensolver of the counter sample (0 automatic, 1 one-stage, "
+                         "2 two-stage)")
     ap.add_argument("--rows", type=int, default=6)
     ap.add_argument("--cols", type=int, default=8)
     ap.add_argument("--chi", type=int, default=1024)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "c64", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "c64", "bf16x3"])
+    ap.add_argument("--compare", default="fp64",
+                    help="precision of the one-step comparison leg on the same start state "
+                         "('none' disables it)")
     ap.add_argument("--theta0", type=float, default=math.pi / 18)
     ap.add_argument("--schedule", type=int, default=2, choices=[1, 2, 4],
                     help="1: wrap pairs routed by SWAPs and back; 2: rotating rows; "
@@ -306,10 +410,10 @@ def main() -> int:
     ap.add_argument("--prof", default="gram", choices=sorted(DOMINANT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=40.0,
                     help="admission window of the served run (0 disables it)")
-    ap.add_argument("--serve-chi-cap", type=int, default=32)
-    ap.add_argument("--serve-requests", type=int, default=8)
+    ap.add_argument("--serve-chi-cap", type=int, default=1024)
+    ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--cube", default="",
                     help="also time the cubic lattice LX,LY,LZ (one qubit per site)")
     ap.add_argument("--cube-chi", type=int, default=64)
@@ -318,128 +422,177 @@ def main() -> int:
                     help="also time the XY-model quench on the LX,LY grid")
     ap.add_argument("--xy-chi", type=int, default=256)
     ap.add_argument("--xy-steps", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=0,
-                    help="also time this many concurrent instances of the workload")
+    ap.add_argument("--instances", type=int, default=4,
+                    help="concurrent instances of the workload in the batched leg (one step "
+                         "each, headline precision; 0 disables it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("this build runs one MPS instance on one GPU; multi-GPU runs are not "
-              "supported (--gpus must be 1)", file=sys.stderr)
+        print("this build runs on one GPU only: multi-GPU runs are not supported "
+              "(--gpus must be 1)", file=sys.stderr)
         return 2
+    deadline = T_PROC0 + args.budget
+
+    def left() -> float:
+        return deadline - time.perf_counter()
+
+    cpu = None
+    if not args.no_cpu_baseline and not args.pmc_sample:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget, args.schedule)
+        log("cpu baseline: %.3e steps/s (%.1fs)" % (cpu["value"], time.perf_counter() - t0))
 
     import torch
     from paper_2511_23438_amd import mpsim
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    cfg = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
-                            precision=args.precision, schedule=args.schedule)
-    sim = mpsim.Simulation(cfg)
-    if args.start == "random" or args.pmc_sample:
+    if args.pmc_sample:
         from paper_2511_23438_amd import workloads
-        centre = args.rows - 1
+        cfg = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
+                                precision="fp64", schedule=args.schedule,
+                                eig_path=args.pmc_eig_path)
+        sim = mpsim.Simulation(cfg)
         sites, centre = workloads.random_mps(args.rows, args.cols, args.chi, args.seed,
-                                             centre=centre)
+                                             centre=args.rows - 1)
         sim.set_state(sites, centre)
         del sites
-        log("random start state loaded, bonds %s" % sim.bond_dims())
-    if args.pmc_sample:
         # calibration: an elementwise kernel that reads 1 GiB and writes 1 GiB
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
+        del x, y
         log("calibration kernel (1 GiB read, 1 GiB written) done")
         t0 = time.perf_counter()
         sim.apply_two_site(args.rows - 1, 1, 1)
         sim.sync()
         log("bulk update done in %.2fs" % (time.perf_counter() - t0))
+        sim.free()
+        torch.cuda.synchronize()
         print(json.dumps({"pmc_sample": True, "workload": "tfim_%dx%d_chi%d" % (
-            args.rows, args.cols, args.chi)}), flush=True)
+            args.rows, args.cols, args.chi), "eig_path": args.pmc_eig_path}), flush=True)
         return 0
-    for w in range(args.warmup):
-        t0 = time.perf_counter()
-        sim.step(1)
-        sim.sync()
-        log("warmup step %d: %.2fs bonds %s" % (w + 1, time.perf_counter() - t0, sim.bond_dims()))
 
-    t_start = [time.perf_counter()]
+    from paper_2511_23438_amd import workloads
+    t0 = time.perf_counter()
+    if args.start == "random":
+        sites, centre = workloads.random_mps(args.rows, args.cols, args.chi, args.seed,
+                                             centre=args.rows - 1)
+    else:
+        sites, centre = None, 0
+    log("start state generated in %.1fs" % (time.perf_counter() - t0))
 
-    def progress(step, upd, n):
-        if upd % 6 == 0 or upd == n:
-            log("  step %d: update %d/%d enqueued, %.1fs" % (step + 1, upd, n,
-                                                           time.perf_counter() - t_start[0]))
-    sim.set_progress(progress)
     # the roofline kernel at the workload's dominant shape: the Gram GEMMs of
     # the widest updates (side n = chi*d, K = n: 4 n^3 flops; the next widest
     # carry less than a tenth of that); other launch classes: every launch
     dblk = 2 ** ((args.cols + 1) // 2)
     nwide = min(args.chi * dblk, dblk ** args.rows)
     if args.schedule == 4:
-        # bond truncations: Gram of the (chi d) x (2 chi) site on its 2 chi side
         gram_max = 4.0 * float(min(2 * args.chi, nwide)) ** 2 * float(nwide)
     else:
         gram_max = 4.0 * float(nwide) ** 3
-    sim.profile(args.prof, min_work=(0.5 * gram_max if args.prof == "gram" else 0.0))
-    torch.cuda.synchronize()
-    t_start[0] = time.perf_counter()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        sim.step(1)
-        obs = sim.measure()          # part of the step: one measurement per step
-        log("step %d: %.2fs since start, <Z>=%.6f <Z^2>=%.6f F=%.4e bonds %s" % (
-            k + 1, time.perf_counter() - t0, obs["z"], obs["z2"], obs["fidelity"],
-            sim.bond_dims()))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_k, launches, work = sim.profile_read()
-    sim.profile("off")
-    elapsed = t1 - t0
-    value = args.steps / elapsed
+    min_work = 0.5 * gram_max if args.prof == "gram" else 0.0
 
-    bound = DOMINANT[args.prof]
-    peak, unit = PEAK[bound]
-    avg_s = (ms_k / 1e3) / max(launches, 1)
-    per_launch = work / max(launches, 1)
-    if bound == "hbm":
-        achieved = per_launch / avg_s / 1e9
+    do_cmp = args.compare != "none" and args.compare != args.precision
+    do_conc = args.instances > 0
+    do_serve = args.serve_seconds > 0
+
+    def reserve(step_s: float) -> float:
+        # deadline of the headline loop: leave room for the later legs
+        r = 10.0
+        if do_cmp:
+            r += 1.3 * step_s + 10.0
+        if do_conc:
+            r += 1.25 * args.instances * step_s + 20.0
+        if do_serve:
+            r += args.serve_seconds + 30.0
+        return deadline - r
+
+    if sites is None:
+        # product start: the warmup steps grow the bonds
+        cfgp = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
+                                 precision=args.precision, schedule=args.schedule)
+        simp = mpsim.Simulation(cfgp)
+        for _ in range(args.warmup):
+            simp.step(1)
+        simp.sync()
+        bonds = simp.bond_dims()
+        sites = [simp.get_site(p) for p in range(len(bonds) - 1)]
+        simp.free()
+        centre = 0
+        warm = 0
     else:
-        achieved = per_launch / avg_s / 1e12
+        warm = min(args.warmup, 1)
+    head = state_rate(sites, centre, args.rows, args.cols, args.chi, args.precision,
+                      args.schedule, args.theta0, warm, args.steps, reserve(0.0), args.prof,
+                      min_work, reserve_fn=reserve)
+    log("headline: %.4f steps/s over %d steps" % (head["steps_per_s"], head["steps"]))
     workload = "tfim_%dx%d_chi%d" % (args.rows, args.cols, args.chi)
-    traffic = read_traffic(args.prof, workload)
-    roof = {"bound": "hbm" if bound == "hbm" else "mfma", "achieved": achieved, "peak": peak,
-            "unit": unit, "frac": achieved / peak, "traffic": traffic,
-            "kernel": args.prof, "launches": launches, "avg_launch_us": avg_s * 1e6,
-            "work_per_launch": per_launch,
-            "kernel_time_share": (ms_k / 1e3) / elapsed}
+    roof = roofline(head["prof"], head["seconds"])
+    roof["traffic"] = read_traffic(args.prof, workload)
+    dtype = {"fp64": "f64", "c64": "c64+f64", "bf16x3": "bf16x3+f64"}[args.precision]
     out = {
-        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "metric": METRIC, "value": head["steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+        "steps": head["steps"], "steps_requested": args.steps,
+        "warmup": head["warmup"], "warmup_requested": args.warmup,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "c64": "c64", "bf16x3": "bf16x3"}[args.precision],
-        "data": "synthetic",
+        "dtype": dtype, "data": "synthetic",
         "config": {"workload": workload, "rows": args.rows, "cols": args.cols,
-                   "d": 2 ** ((args.cols + 1) // 2), "sites": 2 * args.rows, "chi": args.chi,
-                   "precision": args.precision, "theta0": args.theta0, "J": -1.0, "h": 2.0,
+                   "d": dblk, "sites": 2 * args.rows, "chi": args.chi,
+                   "precision": args.precision, "contractions": args.precision,
+                   "truncation": "f64 Gram + eigensolver, f64 fidelity",
+                   "theta0": args.theta0, "J": -1.0, "h": 2.0,
                    "dt": 0.25, "trotter_order": 1,
                    "schedule": {1: "block-pair", 2: "rotating-rows",
                                 4: "gate-by-gate"}[args.schedule],
                    "start": ("seeded random MPS at saturated bonds (seed %d)" % args.seed
-                             if args.start == "random" else "product state")
-                            + (" + %d warmup steps" % args.warmup if args.warmup else "")},
+                             if args.start == "random" else
+                             "product state + %d untimed steps" % args.warmup)},
         "roofline": roof,
-        "observables": {"z": obs["z"], "z2": obs["z2"], "fidelity": obs["fidelity"],
-                        "norm": obs["norm"]},
+        "observables": head["observables"],
+        "budget_s": args.budget,
     }
-    sim.free()
-    if args.serve_seconds > 0:
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if do_cmp and left() > 1.3 * head["ms_per_step"] / 1e3 + 10.0:
+        cmp_ = state_rate(sites, centre, args.rows, args.cols, args.chi, args.compare,
+                          args.schedule, args.theta0, 0, 1, time.perf_counter(), args.prof,
+                          min_work)
+        croof = roofline(cmp_["prof"], cmp_["seconds"])
+        out["compare"] = {"precision": args.compare, "steps": cmp_["steps"],
+                          "steps_per_s": cmp_["steps_per_s"], "ms_per_step": cmp_["ms_per_step"],
+                          "headline_over_compare": head["steps_per_s"] / cmp_["steps_per_s"],
+                          "roofline_frac": croof["frac"],
+                          "observables": cmp_["observables"]}
+        log("compare (%s): %.4f steps/s" % (args.compare, cmp_["steps_per_s"]))
+    elif do_cmp:
+        out["compare"] = {"skipped": "wall budget"}
+    if do_conc and left() > 1.25 * args.instances * head["ms_per_step"] / 1e3 + 20.0:
+        log("concurrent run: %d instances" % args.instances)
+        out["concurrent"] = concurrent_from(sites, centre, args.rows, args.cols, args.chi,
+                                           args.precision, args.schedule, args.instances)
+        ref = out.get("compare", {}).get("steps_per_s") if args.compare == "fp64" else None
+        if args.precision == "fp64":
+            ref = head["steps_per_s"]
+        if ref:
+            out["concurrent"]["aggregate_over_fp64_single"] = out["concurrent"]["steps_per_s"] / ref
+        log("concurrent: %.4f steps/s aggregate" % out["concurrent"]["steps_per_s"])
+    elif do_conc:
+        out["concurrent"] = {"skipped": "wall budget"}
+    del sites
+    if do_serve and left() > args.serve_seconds + 20.0:
         log("served run: %d requests, chi <= %d, admission window %.0fs" % (
             args.serve_requests, args.serve_chi_cap, args.serve_seconds))
-        out["served"] = served(args.serve_seconds, args.serve_chi_cap, args.serve_requests)
+        out["served"] = served(args.serve_seconds, args.serve_chi_cap, args.serve_requests,
+                               hard_stop_s=max(5.0, min(args.serve_seconds + 5.0, left() - 40.0)))
         log("served: %s" % {k: out["served"][k] for k in ("completed", "steps_per_s",
                                                          "step_latency_ms_p50",
                                                          "step_latency_ms_p99")})
+    elif do_serve:
+        out["served"] = {"skipped": "wall budget"}
     if args.cube:
         shape = tuple(int(v) for v in args.cube.split(","))
         log("cube run: %s chi %d" % (shape, args.cube_chi))
@@ -450,14 +603,7 @@ def main() -> int:
         log("XY run: %s chi %d" % (shape, args.xy_chi))
         out["xy"] = xy_rate(shape, args.xy_chi, args.precision, args.xy_steps, args.seed)
         log("xy: %.3f steps/s" % out["xy"]["steps_per_s"])
-    if args.instances > 0:
-        log("concurrent run: %d instances" % args.instances)
-        out["concurrent"] = concurrent(args.rows, args.cols, args.chi, args.precision,
-                                       args.schedule, args.instances, args.seed)
-        log("concurrent: %.3f steps/s aggregate" % out["concurrent"]["steps_per_s"])
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget,
-                                           args.schedule)
+    out["wall_s"] = time.perf_counter() - T_PROC0
     print(json.dumps(out), flush=True)
     return 0
 

@@ -4,6 +4,7 @@ Usage: python -m paper_2511_23438_amd.build  (or call build()).
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -11,6 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpsim.so")
+STAMP = LIB + ".srchash"   # hash of the sources and flags the library was built from
 SOURCES = ["gemm.hip", "linalg.hip", "band.hip", "mps_kernels.hip", "planner.cpp", "mpsim.cpp"]
 ARCH = os.environ.get("MPSIM_OFFLOAD_ARCH", "gfx950")
 
@@ -19,6 +21,30 @@ HIPCC_FLAGS = [
     # keep hipcc from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+
+
+def source_hash() -> str:
+    """sha256 over every file under csrc/, the public header and the flags."""
+    h = hashlib.sha256()
+    files = sorted(os.listdir(CSRC))
+    for f in files:
+        path = os.path.join(CSRC, f)
+        if os.path.isfile(path) and f.endswith((".hip", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(HERE, "..", "include", "mpsim.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()
+
+
+def is_current() -> bool:
+    """True when libmpsim.so exists and was built from the current sources."""
+    if not (os.path.exists(LIB) and os.path.exists(STAMP)):
+        return False
+    with open(STAMP) as fh:
+        return fh.read().strip() == source_hash()
 
 
 def build(verbose: bool = False) -> str:
@@ -38,6 +64,8 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    with open(STAMP, "w") as fh:
+        fh.write(source_hash() + "\n")
     for o in objs:
         os.remove(o)
     return LIB

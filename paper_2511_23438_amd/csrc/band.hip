@@ -367,7 +367,7 @@ static void hb2st_launches(int n, cplx* Ab, hipStream_t s) {
 // The launch sequence depends only on n and the band's address, so it is
 // captured once into a HIP graph (on a private stream) and replayed; if
 // capture or instantiation fails the kernels are launched directly.
-static hipGraphExec_t hb2st_graph(int n, cplx* Ab, LinalgWork& w) {
+static hipGraphExec_t hb2st_graph(int n, cplx* Ab, LinalgWork& w, hipStream_t s) {
   for (auto& g : w.hbg)
     if (g.exec && g.n == n && g.ab == Ab) return g.exec;
   if (!w.cap_stream && hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -389,6 +389,8 @@ static hipGraphExec_t hb2st_graph(int n, cplx* Ab, LinalgWork& w) {
   }
   auto& slot = w.hbg[w.hbg_next];
   w.hbg_next = (w.hbg_next + 1) % 2;
+  // the evicted graph may still be queued or running on the handle's stream
+  if (slot.exec) (void)hipStreamSynchronize(s);
   if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
   if (slot.graph) (void)hipGraphDestroy(slot.graph);
   slot.n = n;
@@ -400,7 +402,7 @@ static hipGraphExec_t hb2st_graph(int n, cplx* Ab, LinalgWork& w) {
 
 void hb2st(int n, cplx* Ab, LinalgWork& w, hipStream_t s) {
   if (n >= 3) {
-    hipGraphExec_t exec = hb2st_graph(n, Ab, w);
+    hipGraphExec_t exec = hb2st_graph(n, Ab, w, s);
     if (!exec || hipGraphLaunch(exec, s) != hipSuccess) {
       (void)hipGetLastError();
       hb2st_launches(n, Ab, s);

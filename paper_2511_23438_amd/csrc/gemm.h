@@ -16,7 +16,9 @@ struct ZOp {
 
 enum { EPI_STORE = 0, EPI_THETA = 1 };
 // arithmetic of the product: float64, complex64 with FP32 accumulation, or a
-// bf16 hi/lo split (hi*hi + hi*lo + lo*hi) with FP32 accumulation
+// three-term bf16 split of each float64 operand (x = hi + mid + lo, each term
+// the bf16 rounding of what the previous terms leave) whose six leading
+// products (hh, hm, mh, hl, lh, mm) are accumulated in FP32
 enum { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };
 
 struct ZGemm {

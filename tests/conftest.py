@@ -14,9 +14,11 @@ def pytest_configure(config):
 
 
 def _ensure_built():
-    lib = os.path.join(ROOT, "paper_2511_23438_amd", "libmpsim.so")
-    if not os.path.exists(lib):
-        from paper_2511_23438_amd import build
+    """Build the library when it is missing or was built from other sources
+    (the build records a hash of its sources next to the library)."""
+    from paper_2511_23438_amd import build
+    if not build.is_current():
+        print("libmpsim.so missing or stale: rebuilding", file=sys.stderr, flush=True)
         build.build()
 
 
