@@ -217,6 +217,16 @@ mps_status mps_apply_two_site(mps_handle h, int32_t site, int32_t swap, int32_t 
 mps_status mps_apply_two_site_toward(mps_handle h, int32_t site, int32_t swap, int32_t gate,
                                      int32_t next_site);
 
+/* Apply the single-site gate of the step schedule to site `site`: variant 0
+ * = U_X(h dt) D_intra, 1 = D_intra U_X(h dt / 2), 2 = U_X(h dt / 2) (the
+ * records of kind 2 in mps_schedule_dump; the gates inside one block, results
+ * section) on the physical leg of the block the site holds. Unitary, so the
+ * canonical form is kept and nothing is truncated. For driving a step op by
+ * op (tests). MPS_E_INVAL for a bad site or variant, MPS_E_UNSUPPORTED for
+ * the XY model (its single-site layers are part of its preparation only).
+ * Asynchronous on the handle's stream. */
+mps_status mps_apply_single_site(mps_handle h, int32_t site, int32_t variant);
+
 /* Per-update truncation fidelities f and relative gaps since init (or
  * mps_set_state), in order; *len receives the count. Synchronises. */
 mps_status mps_truncation_log(mps_handle h, double* f, double* gap, int32_t cap,

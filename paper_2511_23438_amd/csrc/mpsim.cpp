@@ -1129,6 +1129,15 @@ mps_status mps_apply_two_site_toward(mps_handle h, int32_t site, int32_t swap, i
   return MPS_OK;
 }
 
+mps_status mps_apply_single_site(mps_handle h, int32_t site, int32_t variant) {
+  GUARD(h);
+  if (site < 0 || site >= h->plan.N) return fail(h, MPS_E_INVAL, "bad site");
+  if (variant < 0 || variant > 2) return fail(h, MPS_E_INVAL, "variant must be 0, 1 or 2");
+  if (h->plan.model == 1) return fail(h, MPS_E_UNSUPPORTED, "no single-site layer in the XY step");
+  TRYDEV(h, single_site(h, site, variant); HIPCHK(hipGetLastError()));
+  return MPS_OK;
+}
+
 mps_status mps_truncation_log(mps_handle h, double* f, double* gap, int32_t cap, int32_t* len) {
   GUARD(h);
   if (!len) return fail(h, MPS_E_INVAL, "len is NULL");

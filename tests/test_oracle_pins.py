@@ -503,3 +503,116 @@ def test_gate_by_gate_zero_coupling_closed_form():
         assert abs(o["z"] - math.cos(th) * c) < 1e-12
         assert abs(o["z2"] - (1 / g.n + (1 - 1 / g.n) * math.cos(th) ** 2 * c ** 2)) < 1e-12
         assert abs(o["fidelity"] - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# theta_min / theta_from_delta (model section) and the rescaled estimators
+# (eqs. "Z_tot_via_F" and "z2_tot_rescaled")
+def _product_vector(n, th):
+    psi = np.ones(1)
+    for _ in range(n):
+        psi = np.kron(psi, [math.cos(th / 2), math.sin(th / 2)])
+    return psi
+
+
+@pytest.mark.parametrize("J_,h_", [(-1.0, 2.0), (-1.0, 1.0), (-2.0, -3.0), (-0.7, 0.4)])
+def test_theta_min_minimises_product_state_energy(J_, h_):
+    """theta_min is where the energy of the product state of eq.
+    "initial_state" is lowest (the model section's mean-field minimum, four
+    neighbours per qubit): minimise <Psi(theta)|H|Psi(theta)> with the dense
+    Hamiltonian of the periodic 3x3 grid, where every qubit has 4 distinct
+    neighbours, over theta in [-pi/2, pi/2] (ferromagnetic J < 0)."""
+    import scipy.optimize
+    from oracle.lattice import theta_min
+    hzz, hx, _ = _dense_h(3, 3)
+    Hd = J_ * hzz + h_ * hx
+
+    def energy(th):
+        psi = _product_vector(9, th)
+        return float(psi @ Hd @ psi)
+    res = scipy.optimize.minimize_scalar(energy, bounds=(-math.pi / 2, math.pi / 2),
+                                         method="bounded", options={"xatol": 1e-11})
+    assert abs(theta_min(J_, h_) - res.x) < 1e-6
+    # and it is a minimum of the energy on the whole circle
+    grid_th = np.linspace(-math.pi, math.pi, 721)
+    assert energy(theta_min(J_, h_)) <= min(energy(t) for t in grid_th) + 1e-12
+
+
+def test_theta_values_of_the_paper_temperatures():
+    """J = -1, h = 2: theta_min = asin(2 / (4 * -1)) = -pi/6, and the paper's
+    temperatures delta_theta = 0, 2pi/9, 3pi/9 give theta = -pi/6, pi/18,
+    pi/6 (the mid temperature pi/18 is the start angle of the workloads)."""
+    from oracle.lattice import theta_from_delta, theta_min
+    assert abs(theta_min(-1.0, 2.0) + math.pi / 6) < 1e-15
+    for dth, th in [(0.0, -math.pi / 6), (2 * math.pi / 9, math.pi / 18),
+                    (3 * math.pi / 9, math.pi / 6)]:
+        assert abs(theta_from_delta(dth, -1.0, 2.0) - th) < 1e-15
+
+
+def _z_tot_diag(n):
+    x = np.arange(2 ** n)
+    return sum(1.0 - 2.0 * ((x >> (n - 1 - q)) & 1) for q in range(n))
+
+
+@pytest.mark.parametrize("R,C,chi,site", [(3, 3, 6, 2), (2, 4, 3, 1), (3, 4, 5, 3)])
+def test_z_rescaled_single_truncation_identity(R, C, chi, site):
+    """One truncation of an exact state splits it as sqrt(f) psi_MPS +
+    sqrt(1 - f) psi_perp with orthogonal parts (results section). Z_tot is a
+    sum of one-qubit operators, each acting on one side of the cut, so the
+    cross terms vanish and <Z>_exact = F <Z>_MPS + (1 - F) <Z>_perp exactly:
+    the rescaled estimator of eq. "Z_tot_via_F" is the exact value less the
+    discarded part's contribution. Every quantity but F <Z>_MPS comes from
+    dense state vectors."""
+    g = Grid(R, C)
+    n = R * C
+    m = mps.BlockMPS(g, 4 ** n, 0.9, J, H, DT)
+    m.step()
+    m.step()                                      # exact (full bond dimension)
+    m.move_centre(site)
+    exact = copy.deepcopy(m)
+    exact.apply_u2(site, False, True)             # no truncation
+    assert abs(exact.log_fidelity) < 1e-12
+    m.chi = chi
+    f = m.apply_u2(site, False, True)             # truncating the same update
+    assert f < 1 - 1e-6
+    psi_e = exact.to_statevector()
+    psi_m = m.to_statevector()
+    perp = (psi_e - math.sqrt(f) * psi_m) / math.sqrt(1 - f)
+    assert abs(np.vdot(psi_m, perp)) < 1e-12 and abs(np.linalg.norm(perp) - 1) < 1e-10
+    zd = _z_tot_diag(n)
+    z_exact = float(np.real(np.vdot(psi_e, zd * psi_e))) / n
+    z_perp = float(np.real(np.vdot(perp, zd * perp))) / n
+    z_mps = m.measure()["z"]
+    assert abs(estimators.z_rescaled(z_mps, f) + (1 - f) * z_perp - z_exact) < 1e-12
+
+
+def test_rescaled_estimators_at_full_bond_dimension_are_exact():
+    """Full bond dimension: F = 1, so both rescaled estimators equal the exact
+    Trotterised values (state vector) for any gamma (the limit the results
+    section states for chi -> infinity)."""
+    g = Grid(3, 3)
+    m = mps.BlockMPS(g, 4 ** 9, 0.7, J, H, DT)
+    sv = statevector.StateVector(g, 0.7, J, H, DT, 1)
+    for _ in range(3):
+        m.step()
+        sv.step()
+    a, b = m.measure(), sv.measure()
+    assert abs(a["fidelity"] - 1) < 1e-12
+    assert abs(estimators.z_rescaled(a["z"], a["fidelity"]) - b["z"]) < 1e-10
+    for gamma in (0.0, 0.2804, 0.4563, 0.647, 1.0, 2.5):
+        assert abs(estimators.z2_rescaled(a["z2"], a["fidelity"], gamma) - b["z2"]) < 1e-10
+
+
+@pytest.mark.parametrize("F1,F2", [(0.9, 0.5), (0.31, 0.999), (1e-3, 0.2)])
+def test_z2_rescaled_no_exponent_and_step_products(F1, F2):
+    """gamma = 0 leaves <Z^2>_MPS unchanged whatever F; and since F_MPS is a
+    product of step fidelities (results section), rescaling by the factors
+    of two stretches in turn equals rescaling by their product."""
+    z2 = 0.37
+    for F in (F1, F2, F1 * F2):
+        assert estimators.z2_rescaled(z2, F, 0.0) == z2
+    for gamma in (0.2804, 0.647, 1.7):
+        once = estimators.z2_rescaled(z2, F1 * F2, gamma)
+        twice = estimators.z2_rescaled(estimators.z2_rescaled(z2, F1, gamma), F2, gamma)
+        assert abs(once - twice) < 1e-15 * max(1.0, abs(once))
+        assert once < z2                       # F < 1, gamma > 0: a smaller estimate
