@@ -231,6 +231,58 @@ def concurrent_from(sites, centre, rows: int, cols: int, chi: int, precision: st
             "z": [o["z"] for o in obs], "fidelity": [o["fidelity"] for o in obs]}
 
 
+def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0) -> dict:
+    """The batched workload: `count` independent instances (grids 4x5, 5x5,
+    5x6, 6x6 with d 4 and 8, chi in {32, 64, 128, 256}, random J, h, theta0,
+    complex64 contractions), each evolved `steps` Trotter steps from its
+    product state. Batched: every instance on its own stream, all stepped
+    through mps_apply_trotter_step_batched one step at a time (all instances
+    enqueued before any wait). One at a time: the first `alone_sample`
+    instances (all if 0) evolved alone, one after another; the aggregate rate
+    of the whole set is compared on equal work (the steps of those
+    instances). Results of every instance are compared bit for bit between
+    the two runs."""
+    import torch
+    from paper_2511_23438_amd import mpsim, workloads
+    insts = workloads.batched(count, seed=seed)
+    sims, streams = [], []
+    for k, inst in enumerate(insts):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            sims.append(mpsim.Simulation(mpsim.config_from_instance(inst, seed=k),
+                                         stream=st.cuda_stream))
+        streams.append(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mpsim.apply_batched(sims, 1)
+    obs = [s.measure() for s in sims]
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    for s in sims:
+        s.free()
+    nalone = count if alone_sample <= 0 else min(alone_sample, count)
+    t0 = time.perf_counter()
+    same = 0
+    for k in range(nalone):
+        sim = mpsim.Simulation(mpsim.config_from_instance(insts[k], seed=k))
+        sim.step(steps)
+        o = sim.measure()
+        sim.free()
+        same += int(all(o[key] == obs[k][key] for key in ("z", "z2", "log_fidelity")))
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    rate_b = count * steps / t_batched
+    rate_a = nalone * steps / t_alone
+    grids = sorted({"%dx%d" % (i.rows, i.cols) for i in insts})
+    return {"instances": count, "steps_each": steps, "grids": grids,
+            "chis": sorted({i.chi for i in insts}), "precision": "c64",
+            "batched_seconds": t_batched, "batched_steps_per_s": rate_b,
+            "alone_instances": nalone, "alone_seconds": t_alone, "alone_steps_per_s": rate_a,
+            "speedup": rate_b / rate_a, "bitwise_equal_alone_and_batched": same,
+            "min_fidelity": min(o["fidelity"] for o in obs)}
+
+
 def cube_rate(shape: tuple[int, int, int], chi: int, precision: str, steps: int,
               seed: int) -> dict:
     """Trotter steps/s of the cubic lattice with one qubit per site (open
@@ -385,7 +437,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1,
                     help="untimed steps requested; at most one is run from the saturated "
                          "random start state, whose steps already have steady-state shapes")
-    ap.add_argument("--budget", type=float, default=480.0,
+    ap.add_argument("--budget", type=float, default=500.0,
                     help="wall-clock seconds from process start to the JSON line; the timed "
                          "loop and the later legs are cut to fit")
     ap.add_argument("--start", default="random", choices=["random", "product"])
@@ -409,7 +461,7 @@ def main() -> int:
                          "4: gate by gate (rank-2 operators, bond truncations)")
     ap.add_argument("--prof", default="gram", choices=sorted(DOMINANT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--serve-seconds", type=float, default=40.0,
                     help="admission window of the served run (0 disables it)")
     ap.add_argument("--serve-chi-cap", type=int, default=1024)
@@ -422,6 +474,14 @@ def main() -> int:
                     help="also time the XY-model quench on the LX,LY grid")
     ap.add_argument("--xy-chi", type=int, default=256)
     ap.add_argument("--xy-steps", type=int, default=1)
+    ap.add_argument("--batched-set", type=int, default=0,
+                    help="also run the batched workload with this many instances (64 in the "
+                         "workload definition)")
+    ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched workload and print its result")
+    ap.add_argument("--batched-alone", type=int, default=0,
+                    help="instances of the batched set also run one at a time (0: all)")
     ap.add_argument("--instances", type=int, default=4,
                     help="concurrent instances of the workload in the batched leg (one step "
                          "each, headline precision; 0 disables it)")
@@ -438,7 +498,7 @@ def main() -> int:
         return deadline - time.perf_counter()
 
     cpu = None
-    if not args.no_cpu_baseline and not args.pmc_sample:
+    if not args.no_cpu_baseline and not args.pmc_sample and not args.batched_only:
         t0 = time.perf_counter()
         cpu = cpu_baseline(args.rows, args.cols, args.chi, args.cpu_budget, args.schedule)
         log("cpu baseline: %.3e steps/s (%.1fs)" % (cpu["value"], time.perf_counter() - t0))
@@ -447,6 +507,13 @@ def main() -> int:
     from paper_2511_23438_amd import mpsim
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+
+    if args.batched_only:
+        res = batched_set(args.batched_set or 64, args.batched_steps,
+                          alone_sample=args.batched_alone)
+        print(json.dumps({"batched_set": res, "wall_s": time.perf_counter() - T_PROC0}),
+              flush=True)
+        return 0
 
     if args.pmc_sample:
         from paper_2511_23438_amd import workloads
@@ -593,6 +660,13 @@ def main() -> int:
                                                          "step_latency_ms_p99")})
     elif do_serve:
         out["served"] = {"skipped": "wall budget"}
+    if args.batched_set > 0:
+        log("batched set: %d instances x %d steps" % (args.batched_set, args.batched_steps))
+        out["batched_set"] = batched_set(args.batched_set, args.batched_steps,
+                                         alone_sample=args.batched_alone)
+        log("batched set: %s" % {k: out["batched_set"][k] for k in (
+            "batched_steps_per_s", "alone_steps_per_s", "speedup",
+            "bitwise_equal_alone_and_batched")})
     if args.cube:
         shape = tuple(int(v) for v in args.cube.split(","))
         log("cube run: %s chi %d" % (shape, args.cube_chi))

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpsim.so")
 STAMP = LIB + ".srchash"   # hash of the sources and flags the library was built from
-SOURCES = ["gemm.hip", "linalg.hip", "band.hip", "mps_kernels.hip", "planner.cpp", "mpsim.cpp"]
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 ARCH = os.environ.get("MPSIM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -27,6 +27,11 @@ using namespace mpsim;
 
 static thread_local std::string g_tl_error;
 
+namespace mpsim {
+// Message returned by mps_last_error(NULL) on this thread (calls without a handle).
+void set_thread_error(const std::string& msg) { g_tl_error = msg; }
+}  // namespace mpsim
+
 struct mps_sim {
   mps_config cfg{};
   Plan plan;

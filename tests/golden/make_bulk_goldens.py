@@ -1,6 +1,7 @@
-"""Oracle results of single bulk two-site updates of the 6x8 grid (d = 16)
-at the bond dimensions of the metric workload: Gram sides 4096 (chi = 256),
-8192 (chi = 512) and 16384 (chi = 1024), each with and without SWAP.
+"""Oracle results of single bulk two-site updates at the shapes of the
+workloads: the 6x8 grid (d = 16) at Gram sides 4096 (chi = 256), 8192
+(chi = 512) and 16384 (chi = 1024), and the 5x6 grid (d = 8) at Gram sides
+2048 (chi = 256) and 4096 (chi = 512), each with and without SWAP.
 
 For each case: the seeded random MPS in mixed canonical form with the
 centre on the update's site (workloads.random_mps), the update on (site,
@@ -16,7 +17,7 @@ Calls only oracle/ and the seeded input generator. Usage (from the
 repository root, takes about an hour on 8 cores, ~30 GB of memory at the
 largest case):
 
-    python tests/golden/make_bulk_goldens.py [chi ...]
+    python tests/golden/make_bulk_goldens.py [RxC:chi ...]
 """
 from __future__ import annotations
 
@@ -36,24 +37,27 @@ from oracle.lattice import Grid         # noqa: E402
 from paper_2511_23438_amd import workloads  # noqa: E402
 
 J, H, DT = -1.0, 2.0, 0.25
-ROWS, COLS, SITE = 6, 8, 5
 NSAMPLES = 64
-CASES = [  # (chi, swap, seed)
-    (256, 0, 4101), (256, 1, 4102),
-    (512, 1, 4103), (512, 0, 4104),
-    (1024, 1, 4105), (1024, 0, 4106),
+CASES = [  # (rows, cols, chi, swap, seed); the update acts on sites (rows - 1, rows)
+    (6, 8, 256, 0, 4101), (6, 8, 256, 1, 4102),
+    (6, 8, 512, 1, 4103), (6, 8, 512, 0, 4104),
+    (6, 8, 1024, 1, 4105), (6, 8, 1024, 0, 4106),
+    (5, 6, 256, 1, 4201), (5, 6, 256, 0, 4202),
+    (5, 6, 512, 1, 4203), (5, 6, 512, 0, 4204),
 ]
 
 
-def golden_path(chi: int, swap: int) -> str:
+def golden_path(rows: int, cols: int, chi: int, swap: int) -> str:
     return os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                        "bulk_update_6x8_chi%d_%s.json" % (chi, "swap" if swap else "noswap"))
+                        "bulk_update_%dx%d_chi%d_%s.json" % (rows, cols, chi,
+                                                             "swap" if swap else "noswap"))
 
 
-def make(chi: int, swap: int, seed: int) -> dict:
+def make(rows: int, cols: int, chi: int, swap: int, seed: int) -> dict:
     t0 = time.perf_counter()
-    sites, centre = workloads.random_mps(ROWS, COLS, chi, seed, centre=SITE)
-    grid = Grid(ROWS, COLS)
+    SITE = rows - 1
+    sites, centre = workloads.random_mps(rows, cols, chi, seed, centre=SITE)
+    grid = Grid(rows, cols)
     m = omps.BlockMPS.from_sites(grid, chi, sites, centre, J, H, DT)
     blocks = (m.pos[SITE], m.pos[SITE + 1])
     del sites
@@ -70,7 +74,7 @@ def make(chi: int, swap: int, seed: int) -> dict:
     Bm = B.reshape(q, cols_)
     vals = np.einsum('kq,qk->k', Am[r], Bm[:, c])
     out = {
-        "grid": [ROWS, COLS], "chi": chi, "seed": seed, "centre": SITE, "site": SITE,
+        "grid": [rows, cols], "chi": chi, "seed": seed, "centre": SITE, "site": SITE,
         "swap": swap, "gate": 1, "J": J, "h": H, "dt": DT,
         "blocks": [int(blocks[0]), int(blocks[1])],
         "theta_shape": [int(rows_), int(cols_)],
@@ -86,13 +90,13 @@ def make(chi: int, swap: int, seed: int) -> dict:
 
 
 def main() -> None:
-    want = {int(a) for a in sys.argv[1:]}
-    for chi, swap, seed in CASES:
-        if want and chi not in want:
+    want = set(sys.argv[1:])
+    for rows, cols, chi, swap, seed in CASES:
+        if want and "%dx%d:%d" % (rows, cols, chi) not in want:
             continue
-        path = golden_path(chi, swap)
-        print("chi %d swap %d seed %d ..." % (chi, swap, seed), flush=True)
-        out = make(chi, swap, seed)
+        path = golden_path(rows, cols, chi, swap)
+        print("%dx%d chi %d swap %d seed %d ..." % (rows, cols, chi, swap, seed), flush=True)
+        out = make(rows, cols, chi, swap, seed)
         with open(path, "w") as fh:
             json.dump(out, fh, indent=0)
         print("  f = %.17g  q = %d  gap = %.3e  (%.0fs) -> %s" % (

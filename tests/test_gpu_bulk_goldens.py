@@ -24,7 +24,7 @@ from paper_2511_23438_amd import mpsim, workloads
 
 pytestmark = pytest.mark.gpu
 GOLDEN = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden",
-                                       "bulk_update_6x8_chi*.json")))
+                                       "bulk_update_*.json")))
 
 
 def say(*a):
@@ -74,5 +74,58 @@ def test_bulk_update_matches_oracle(path):
         e1 = np.max(np.abs(sv[big] - gsv[big]))
         say("kept singular values: squared error %.2e, error above 1e-3 %.2e" % (e2, e1))
         assert e2 < 1e-12 and e1 < 1e-10
+    finally:
+        sim.free()
+
+
+def _reduced_cases():
+    out = []
+    for p in GOLDEN:
+        name = os.path.basename(p)
+        if name.startswith("bulk_update_5x6_"):
+            out.append((p, "c64"))
+        elif name.startswith("bulk_update_6x8_chi256") or name.startswith("bulk_update_6x8_chi512"):
+            out.append((p, "bf16x3"))
+    return out
+
+
+RED = _reduced_cases()
+
+
+@pytest.mark.parametrize("path,prec", RED,
+                         ids=["%s-%s" % (os.path.basename(p)[12:-5], q) for p, q in RED])
+def test_bulk_update_reduced_precision(path, prec):
+    """The same updates with the contractions in complex64 (the 5x6
+    workload) or the three-term bf16 split (the 6x8 workload), FP32
+    accumulation, and the float64 truncation: f, the sampled block entries
+    (relative to the largest) and the kept singular values within 1e-5
+    relative of the float64 oracle, each error printed."""
+    gold = json.load(open(path))
+    R, C = gold["grid"]
+    chi, site = gold["chi"], gold["site"]
+    sites, centre = workloads.random_mps(R, C, chi, gold["seed"], centre=gold["centre"])
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, J=gold["J"], h=gold["h"],
+                                             dt=gold["dt"], theta0=0.0, precision=prec))
+    try:
+        sim.set_state(sites, centre)
+        del sites
+        sim.apply_two_site(site, bool(gold["swap"]), bool(gold["gate"]))
+        f = sim.truncation_log()[0][-1]
+        ef = abs(f - gold["f"]) / gold["f"]
+        A, B = sim.get_site(site), sim.get_site(site + 1)
+        q = A.shape[2]
+        Am, Bm = A.reshape(-1, q), B.reshape(q, -1)
+        smp = np.array(gold["samples"])
+        r, c = smp[:, 0].astype(np.int64), smp[:, 1].astype(np.int64)
+        got = np.einsum('kq,qk->k', Am[r], Bm[:, c])
+        want = smp[:, 2] + 1j * smp[:, 3]
+        et = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        del A, B, Am, Bm
+        sv = sim.bond_spectrum(site + 1)
+        gsv = np.array(gold["sv_kept"])
+        es = np.max(np.abs(sv - gsv)) / gsv[0]
+        say("%s %s: f rel err %.2e, block entries rel err %.2e, singular values rel err %.2e"
+            % (os.path.basename(path), prec, ef, et, es))
+        assert ef < 1e-5 and et < 1e-5 and es < 1e-5
     finally:
         sim.free()

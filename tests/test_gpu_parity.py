@@ -176,7 +176,11 @@ def test_config_4x4_chi16_every_update_replayed(seed):
     even where the cut falls inside a degenerate multiplet, so all 640
     updates are compared at the float64 tolerance; after every step the
     oracle measures the GPU's state (observables) and the rescaled estimators
-    are compared with the oracle's, with F the product of the oracle's f."""
+    are compared with the oracle's, with F the product of the oracle's f.
+    Where the cut is not degenerate the truncated state is unique, so the new
+    state itself is compared (state vectors), also when the kept values hold
+    degenerate multiplets (the lattice symmetries of the product state make
+    many)."""
     from oracle import estimators
     inst = workloads.small_4x4(seed) if seed is not None else workloads.Instance(
         4, 4, 16, theta0=math.pi / 18)
@@ -186,8 +190,8 @@ def test_config_4x4_chi16_every_update_replayed(seed):
     ops = mpsim.schedule_dump(cfg, steps)
     per_step = len(ops) // steps
     log_f = 0.0
-    ferr = oerr = 0.0
-    nup = 0
+    ferr = oerr = terr = 0.0
+    nup = ncompared = nclustered = 0
     min_gap = math.inf
     for s_ in range(steps):
         recs = ops[s_ * per_step:(s_ + 1) * per_step]
@@ -203,7 +207,8 @@ def test_config_4x4_chi16_every_update_replayed(seed):
             ora = _oracle_from_gpu(sim, R, C, chi)
             assert (ora.pos[site], ora.pos[site + 1]) == (int(rec[4]), int(rec[5]))
             f_ora = ora.apply_u2(site, bool(swap), bool(gate))
-            min_gap = min(min_gap, ora.update_log[-1]["gap"])
+            rec_o = ora.update_log[-1]
+            min_gap = min(min_gap, rec_o["gap"])
             sim.apply_two_site(site, bool(swap), bool(gate), nxt)
             nup += 1
             f_gpu = sim.truncation_log()[0]
@@ -211,6 +216,17 @@ def test_config_4x4_chi16_every_update_replayed(seed):
             ferr = max(ferr, abs(f_gpu[-1] - f_ora))
             assert abs(f_gpu[-1] - f_ora) < TOL, (s_, k, f_gpu[-1], f_ora)
             log_f += math.log(f_ora)
+            if rec_o["gap"] > 1e-6:
+                # unique truncated state: the whole new state agrees (state
+                # vectors, gauge invariant), also where the kept spectrum
+                # holds degenerate multiplets
+                sv = rec_o["sv"][:rec_o["q"]]
+                clustered = bool(np.any(np.diff(sv) > -1e-10 * sv[0]))
+                err = float(np.max(np.abs(sim.to_statevector() - ora.to_statevector())))
+                terr = max(terr, err)
+                assert err < TOL, (s_, k, err)
+                nclustered += clustered
+                ncompared += 1
         o = sim.measure(gamma=gamma)
         ref = _oracle_from_gpu(sim, R, C, chi).measure()
         F = math.exp(log_f)
@@ -221,7 +237,9 @@ def test_config_4x4_chi16_every_update_replayed(seed):
             assert abs(o[key] - want) < TOL, (s_, key, o[key], want)
         assert abs(o["norm"] - 1) < 1e-12
     print("4x4 chi16 seed", seed, "updates", nup, "smallest relative gap %.2e" % min_gap,
-          "max f err %.2e" % ferr, "max observable err %.2e" % oerr)
+          "max f err %.2e" % ferr, "max observable err %.2e" % oerr,
+          "states compared %d (%d with degenerate kept values), max err %.2e" % (
+              ncompared, nclustered, terr))
     assert nup == steps * 32
     # the same program through the step entry point gives the same numbers
     sim2 = mpsim.Simulation(cfg)
