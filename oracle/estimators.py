@@ -5,6 +5,14 @@
                                                          (eq. "z2_tot_rescaled")
   * gamma_fit = a * log2(chi) / n + b with (a, b) per initial temperature from
     the paper's table of gamma scaling ("tab:gamma_scaling").
+
+Test infrastructure only (tests, the smoke check and the CPU baseline use
+it). Pins: z_rescaled by the results section's single-truncation identity
+<Z>_exact = F <Z>_MPS + (1 - F) <Z>_perp and by full bond dimension;
+z2_rescaled by full bond dimension (F = 1), gamma = 0 and products of step
+fidelities; gamma_fit by the printed values. The exponent of z2_rescaled at
+F < 1 and gamma > 0 has no closed form to compare with: parity partially
+unpinned there.
 """
 from __future__ import annotations
 
