@@ -1,0 +1,66 @@
+"""The allocation-free measurement entry point (mps_measure_static, for
+callers that cannot allocate device memory) against the handle's
+measurement (mps_measure) on the same states, through the C-ABI: two calls
+in a row, the second with a smaller MPS, at the float64 tolerance."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2511_23438_amd import mpsim, workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+_lib = mpsim._lib
+_lib.mps_measure_static.restype = C.c_int
+_lib.mps_measure_static.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
+
+
+def _measure_static(sites_dev, bonds, dims, out, stream):
+    n = len(dims)
+    bb = (C.c_int32 * (n + 1))(*bonds)
+    dd = (C.c_int32 * n)(*dims)
+    pp = (C.c_void_p * n)(*[t.data_ptr() for t in sites_dev])
+    return _lib.mps_measure_static(n, bb, dd, pp, C.c_void_p(stream), C.c_void_p(out.data_ptr()))
+
+
+@pytest.mark.parametrize("order", ["larger_first"])
+def test_measure_static_matches_measure(order):
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    out = torch.full((3,), float("nan"), dtype=torch.float64, device="cuda")
+    for (R, Cc, chi, seed) in [(6, 8, 256, 41), (3, 4, 12, 42)]:
+        sites, centre = workloads.random_mps(R, Cc, chi, seed, centre=R)
+        sim = mpsim.Simulation(mpsim.make_config(R, Cc, chi))
+        sim.set_state(sites, centre)
+        sim.step(1)                       # a state the library produced, centre moved
+        ref = sim.measure()
+        bonds = sim.bond_dims()
+        got_sites = [sim.get_site(p) for p in range(len(bonds) - 1)]
+        sim.free()
+        dims = [a.shape[1] for a in got_sites]
+        dev = [torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to("cuda") for a in got_sites]
+        st = _measure_static(dev, bonds, dims, out, stream)
+        assert st == 0, _lib.mps_last_error(None)
+        torch.cuda.synchronize()
+        norm, z, z2 = out.cpu().tolist()
+        print("%dx%d chi %d: norm %.3e z %.3e z2 %.3e" % (
+            R, Cc, chi, abs(norm - ref["norm"]), abs(z - ref["z"]), abs(z2 - ref["z2"])))
+        assert abs(norm - ref["norm"]) < TOL
+        assert abs(z - ref["z"]) < TOL
+        assert abs(z2 - ref["z2"]) < TOL
+
+
+def test_measure_static_rejects_what_does_not_fit():
+    """A sweep that needs more than the static buffer is refused before any
+    device work; so are malformed arguments."""
+    out = torch.zeros(3, dtype=torch.float64, device="cuda")
+    big = [torch.zeros(1, dtype=torch.complex128, device="cuda")] * 3
+    # bonds 1, 1024, 1024, 1 with d = 16: environments of 3 * 1024^2 complex
+    st = _measure_static(big, [1, 1024, 1024, 1], [16, 16, 16], out, 0)
+    assert st == mpsim.MPS_E_UNSUPPORTED
+    assert b"static buffer" in _lib.mps_last_error(None)
+    assert _measure_static(big, [2, 4, 4, 1], [2, 2, 2], out, 0) == mpsim.MPS_E_INVAL
+    assert _measure_static(big, [1, 4, 4, 1], [2, 3, 2], out, 0) == mpsim.MPS_E_INVAL
