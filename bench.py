@@ -231,17 +231,18 @@ def concurrent_from(sites, centre, rows: int, cols: int, chi: int, precision: st
             "z": [o["z"] for o in obs], "fidelity": [o["fidelity"] for o in obs]}
 
 
-def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0) -> dict:
+def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
+                graphs: int = 1) -> dict:
     """The batched workload: `count` independent instances (grids 4x5, 5x5,
     5x6, 6x6 with d 4 and 8, chi in {32, 64, 128, 256}, random J, h, theta0,
     complex64 contractions), each evolved `steps` Trotter steps from its
-    product state. Batched: every instance on its own stream, all stepped
+    product state, with steps captured as HIP graphs per shape signature when
+    `graphs` is 1. Batched: every instance on its own stream, all stepped
     through mps_apply_trotter_step_batched one step at a time (all instances
-    enqueued before any wait). One at a time: the first `alone_sample`
-    instances (all if 0) evolved alone, one after another; the aggregate rate
-    of the whole set is compared on equal work (the steps of those
-    instances). Results of every instance are compared bit for bit between
-    the two runs."""
+    enqueued, then one synchronisation per step). One at a time: the first
+    `alone_sample` instances (all if 0) evolved alone, one after another; the
+    aggregate rates are compared per instance-step. Results of those
+    instances are compared bit for bit between the two runs."""
     import torch
     from paper_2511_23438_amd import mpsim, workloads
     insts = workloads.batched(count, seed=seed)
@@ -249,34 +250,41 @@ def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0)
     for k, inst in enumerate(insts):
         st = torch.cuda.Stream()
         with torch.cuda.stream(st):
-            sims.append(mpsim.Simulation(mpsim.config_from_instance(inst, seed=k),
+            sims.append(mpsim.Simulation(mpsim.config_from_instance(inst, seed=k, graphs=graphs),
                                          stream=st.cuda_stream))
         streams.append(st)
     torch.cuda.synchronize()
+    log("batched set: %d instances created" % count)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         mpsim.apply_batched(sims, 1)
+        torch.cuda.synchronize()
+        log("batched set: step %d done, %.1fs" % (k + 1, time.perf_counter() - t0))
     obs = [s.measure() for s in sims]
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
+    stats = [s.graph_stats() for s in sims]
     for s in sims:
         s.free()
     nalone = count if alone_sample <= 0 else min(alone_sample, count)
     t0 = time.perf_counter()
     same = 0
     for k in range(nalone):
-        sim = mpsim.Simulation(mpsim.config_from_instance(insts[k], seed=k))
+        sim = mpsim.Simulation(mpsim.config_from_instance(insts[k], seed=k, graphs=graphs))
         sim.step(steps)
         o = sim.measure()
         sim.free()
         same += int(all(o[key] == obs[k][key] for key in ("z", "z2", "log_fidelity")))
+        log("batched set: instance %d alone done, %.1fs" % (k, time.perf_counter() - t0))
     torch.cuda.synchronize()
     t_alone = time.perf_counter() - t0
     rate_b = count * steps / t_batched
     rate_a = nalone * steps / t_alone
     grids = sorted({"%dx%d" % (i.rows, i.cols) for i in insts})
     return {"instances": count, "steps_each": steps, "grids": grids,
-            "chis": sorted({i.chi for i in insts}), "precision": "c64",
+            "chis": sorted({i.chi for i in insts}), "precision": "c64", "graphs": graphs,
+            "graph_captures": int(sum(c for c, _ in stats)),
+            "graph_replays": int(sum(r for _, r in stats)),
             "batched_seconds": t_batched, "batched_steps_per_s": rate_b,
             "alone_instances": nalone, "alone_seconds": t_alone, "alone_steps_per_s": rate_a,
             "speedup": rate_b / rate_a, "bitwise_equal_alone_and_batched": same,
@@ -478,6 +486,8 @@ def main() -> int:
                     help="also run the batched workload with this many instances (64 in the "
                          "workload definition)")
     ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--batched-graphs", type=int, default=1, choices=[0, 1],
+                    help="capture the batched instances' steps as HIP graphs")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload and print its result")
     ap.add_argument("--batched-alone", type=int, default=0,
@@ -510,7 +520,7 @@ def main() -> int:
 
     if args.batched_only:
         res = batched_set(args.batched_set or 64, args.batched_steps,
-                          alone_sample=args.batched_alone)
+                          alone_sample=args.batched_alone, graphs=args.batched_graphs)
         print(json.dumps({"batched_set": res, "wall_s": time.perf_counter() - T_PROC0}),
               flush=True)
         return 0
@@ -663,7 +673,8 @@ def main() -> int:
     if args.batched_set > 0:
         log("batched set: %d instances x %d steps" % (args.batched_set, args.batched_steps))
         out["batched_set"] = batched_set(args.batched_set, args.batched_steps,
-                                         alone_sample=args.batched_alone)
+                                         alone_sample=args.batched_alone,
+                                         graphs=args.batched_graphs)
         log("batched set: %s" % {k: out["batched_set"][k] for k in (
             "batched_steps_per_s", "alone_steps_per_s", "speedup",
             "bitwise_equal_alone_and_batched")})

@@ -471,12 +471,10 @@ __device__ inline void stage_b_bf(__bf16 (*Bs)[BN][KP], const cplx r[4], int kof
   }
 }
 
-__device__ inline bf8 ld8(const __bf16* p) {
-  bf8 v;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = p[e];
-  return v;
-}
+// eight consecutive bf16 of an LDS row in one 128-bit load (rows are KP = 40
+// elements long and the offsets multiples of 8, so every address is 16-byte
+// aligned)
+__device__ inline bf8 ld8(const __bf16* p) { return *reinterpret_cast<const bf8*>(p); }
 
 // acc += x * y for split operands x = (xh, xm, xl), y = (yh, ym, yl)
 __device__ inline f4 mfma_split3(const bf8* x, const bf8* y, f4 acc) {
@@ -492,8 +490,8 @@ __device__ inline f4 mfma_split3(const bf8* x, const bf8* y, f4 acc) {
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
   const ZGemm& g = gd.g;
-  __shared__ __bf16 As[6][BM][KP];
-  __shared__ __bf16 Bs[9][BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[9][BN][KP];
   const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
   if (g.lower_only && n0 >= m0 + BM) return;
   if (g.upper_only && m0 >= n0 + BN) return;
@@ -514,22 +512,30 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
       cr[a][b] = (f4){0, 0, 0, 0};
       ci[a][b] = (f4){0, 0, 0, 0};
     }
+  // the operands of the next K stage are loaded (clamped addresses, always
+  // valid) before the products of the current one and staged one step later
+  cplx ra0[4], rb0[4], ra1[4], rb1[4];
+  load_a<TA>(g, A, m0, kbeg, kend, ra0);
+  load_b<TB>(g, B, n0, kbeg, kend, rb0);
+  load_a<TA>(g, A, m0, kbeg + BK, kend, ra1);
+  load_b<TB>(g, B, n0, kbeg + BK, kend, rb1);
   for (long k0 = kbeg; k0 < kend; k0 += BK2) {
-    cplx ra[4], rb[4];
     __syncthreads();
-    load_a<TA>(g, A, m0, k0, kend, ra);
-    load_b<TB>(g, B, n0, k0, kend, rb);
-    fix_a<TA>(g, m0, k0, kend, ra);
-    fix_b<TB>(g, n0, k0, kend, rb);
-    stage_a_bf<TA>(As, ra, 0, g.A.conj);
-    stage_b_bf<TB>(Bs, rb, 0, g.B.conj);
-    load_a<TA>(g, A, m0, k0 + BK, kend, ra);
-    load_b<TB>(g, B, n0, k0 + BK, kend, rb);
-    fix_a<TA>(g, m0, k0 + BK, kend, ra);
-    fix_b<TB>(g, n0, k0 + BK, kend, rb);
-    stage_a_bf<TA>(As, ra, BK, g.A.conj);
-    stage_b_bf<TB>(Bs, rb, BK, g.B.conj);
+    fix_a<TA>(g, m0, k0, kend, ra0);
+    fix_b<TB>(g, n0, k0, kend, rb0);
+    stage_a_bf<TA>(As, ra0, 0, g.A.conj);
+    stage_b_bf<TB>(Bs, rb0, 0, g.B.conj);
+    fix_a<TA>(g, m0, k0 + BK, kend, ra1);
+    fix_b<TB>(g, n0, k0 + BK, kend, rb1);
+    stage_a_bf<TA>(As, ra1, BK, g.A.conj);
+    stage_b_bf<TB>(Bs, rb1, BK, g.B.conj);
     __syncthreads();
+    if (k0 + BK2 < kend) {
+      load_a<TA>(g, A, m0, k0 + BK2, kend, ra0);
+      load_b<TB>(g, B, n0, k0 + BK2, kend, rb0);
+      load_a<TA>(g, A, m0, k0 + BK2 + BK, kend, ra1);
+      load_b<TB>(g, B, n0, k0 + BK2 + BK, kend, rb1);
+    }
     const int kq = 8 * (l >> 4);
     bf8 are[2][3], aim[2][3];
 #pragma unroll

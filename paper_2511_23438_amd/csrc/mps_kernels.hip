@@ -228,8 +228,10 @@ void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStre
   hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(256), 0, s, (const double*)partial, NORM_BLOCKS, dst);
 }
 
-__global__ void k_trunc_finalize(double* sc, double* flog, long idx, const double* lam, int q, int extra,
+__global__ void k_trunc_finalize(double* sc, double* flog, int* count, const double* lam, int q, int extra,
                                  int* flag) {
+  const int idx = *count;  // the log position is kept on the device (graph replays reuse launches)
+  *count = idx + 1;
   const double nM = sc[2], nC = sc[3];
   const double f = nC / nM;
   double gap = INFINITY;
@@ -245,9 +247,9 @@ __global__ void k_trunc_finalize(double* sc, double* flog, long idx, const doubl
   flog[2 * idx + 1] = gap;
 }
 
-void launch_trunc_finalize(double* sc, double* flog, long idx, const double* lam, int q, int extra,
+void launch_trunc_finalize(double* sc, double* flog, int* count, const double* lam, int q, int extra,
                            int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_trunc_finalize, dim3(1), dim3(1), 0, s, sc, flog, idx, lam, q, extra, flag);
+  hipLaunchKernelGGL(k_trunc_finalize, dim3(1), dim3(1), 0, s, sc, flog, count, lam, q, extra, flag);
 }
 
 __global__ void k_scale_by(cplx* x, long len, const double* sc) {

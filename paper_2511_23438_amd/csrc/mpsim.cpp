@@ -46,6 +46,7 @@ struct mps_sim {
   int centre = 0;
   int steps = 0;
   uint64_t nupdates = 0;
+  uint64_t step_upd = 0;   // truncations since the start of the current step (seeds the eigensolver)
 
   long tmp_elems = 0, theta_elems = 0, gram_elems = 0, env_elems = 0, envx_elems = 0;
   cplx* theta = nullptr;
@@ -58,6 +59,7 @@ struct mps_sim {
   double* dscal = nullptr;   // [0] logF [1] min gap [2] |M|^2 [3] |C|^2 [4] 1/|C|
   double* dpartial = nullptr;
   double* flog = nullptr;
+  int* dlogn = nullptr;     // device copy of nlog: the next log position
   long log_cap = 0, nlog = 0;
   LinalgWork lw;
   Prof prof;
@@ -72,6 +74,21 @@ struct mps_sim {
   std::vector<long> zsum_off;
 
   int gprec = GEMM_F64;     // arithmetic of the contractions (theta, C, measurement)
+
+  // steps captured as HIP graphs, keyed by the state's shape signature
+  struct StepGraph {
+    std::vector<int> key;   // bonds, block order, centre before the step
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> bond_after, pos_after;
+    int centre_after = 0;
+    long nlog_delta = 0;
+    uint64_t nupd_delta = 0, step_upd_after = 0;
+    int nu2 = 0;
+  };
+  std::vector<StepGraph> graphs;
+  size_t graph_next = 0;
+  bool graphs_eligible = false;  // no step can take the two-stage eigensolver
+  int64_t graph_captures = 0, graph_replays = 0;
   mps_progress_fn progress = nullptr;
   void* progress_ctx = nullptr;
 
@@ -244,13 +261,38 @@ void norm2(mps_sim* h, const cplx* x, long len, int slot) {
   launch_norm2(x, len, h->dpartial, h->dscal + slot, h->stream);
 }
 
+void release_graphs(mps_sim* h) {
+  if (h->graphs.empty()) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& g : h->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+  h->graph_next = 0;
+}
+
+void dev_free(mps_sim* h, void* p) {
+  auto it = std::find(h->allocations.begin(), h->allocations.end(), p);
+  if (it == h->allocations.end()) return;
+  h->allocations.erase(it);
+  if (h->has_alloc) {
+    h->alloc.free(h->alloc.ctx, p, (void*)h->stream);   // stream-ordered
+  } else {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(p);
+  }
+}
+
+// Capacity of the truncation log; growing it moves the log, so captured step
+// graphs (which hold its address) are released.
 void ensure_log(mps_sim* h, long need) {
   if (need <= h->log_cap) return;
   long ncap = std::max(need, 2 * h->log_cap);
   double* nl = dalloc<double>(h, 2 * ncap);
   if (h->nlog > 0)
     HIPCHK(hipMemcpyAsync(nl, h->flog, sizeof(double) * 2 * h->nlog, hipMemcpyDeviceToDevice, h->stream));
-  h->flog = nl;  // old buffer stays owned by the handle until mps_free
+  release_graphs(h);
+  if (h->flog) dev_free(h, h->flog);
+  h->flog = nl;
   h->log_cap = ncap;
 }
 
@@ -427,7 +469,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     zgemm(gc, nullptr, 0, s, &h->prof);
     launch_unpermute_rows(h->tmpB, A, (int)b0, d, q, s);
     norm2(h, h->theta, (long)q * ldb, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
     launch_scale_by(h->theta, (long)q * ldb, h->dscal, s);
     HIPCHK(hipMemcpyAsync(B, h->theta, sizeof(cplx) * (size_t)q * ldb, hipMemcpyDeviceToDevice, s));
     h->centre = i + 1;
@@ -450,13 +492,14 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     // site i+1 = V^H (q x d b2)
     launch_conj_transpose(h->tmpB, (int)kg, q, q, B, kg, s);
     norm2(h, h->theta, b0 * d * q, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
     launch_scale_by(h->theta, b0 * d * q, h->dscal, s);
     HIPCHK(hipMemcpyAsync(A, h->theta, sizeof(cplx) * (size_t)(b0 * d * q), hipMemcpyDeviceToDevice, s));
     h->centre = i;
   }
   h->nlog += 1;
   h->nupdates += 1;
+  h->step_upd += 1;
   h->bond[i + 1] = q;
   return true;
 }
@@ -474,7 +517,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
   bool left;
   if (mo != no) left = mo < no;
   else left = !(next_site >= 0 && next_site < i);
-  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->nupdates;
+  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->step_upd;
   if (!swap && two_site_factored(h, i, gate, left, q, seed)) return;
 
   // theta
@@ -516,7 +559,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i + 1], (long)q * no, 3);
     ensure_log(h, h->nlog + 1);
-    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
     launch_scale_by(h->site[i + 1], (long)q * no, h->dscal, s);
     h->centre = i + 1;
   } else {
@@ -536,12 +579,13 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i], mo * q, 3);
     ensure_log(h, h->nlog + 1);
-    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
     launch_scale_by(h->site[i], mo * q, h->dscal, s);
     h->centre = i;
   }
   h->nlog += 1;
   h->nupdates += 1;
+  h->step_upd += 1;
   h->bond[i + 1] = q;
   if (swap) std::swap(h->pos[i], h->pos[i + 1]);
 }
@@ -562,7 +606,7 @@ void truncate_bond(mps_sim* h, int i) {
   const long m = (long)b0 * d, n2 = (long)d2 * b2;
   const int q = (int)std::min<long>(std::min<long>(p.chi, p.rank_cap[i + 1]), std::min<long>(m, k));
   const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
-  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->nupdates;
+  const uint64_t seed = h->cfg.seed * 0x9E3779B97F4A7C15ULL + h->step_upd;
   cplx* M = h->site[i];
   norm2(h, M, m * k, 2);
   ensure_log(h, h->nlog + 1);
@@ -578,7 +622,7 @@ void truncate_bond(mps_sim* h, int i) {
     ZGemm gc = zgemm_args(q, k, kg, zop(h->tmpB, q, 1, 1), zop(M, k, 0), h->theta, k, 0, one, zero);
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->theta, (long)q * k, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
     HIPCHK(hipMemcpyAsync(M, h->tmpB, sizeof(cplx) * (size_t)m * q, hipMemcpyDeviceToDevice, s));
   } else {
     const int kg = k;
@@ -592,7 +636,7 @@ void truncate_bond(mps_sim* h, int i) {
     ZGemm gx = zgemm_args((int)m, q, kg, zop(M, k, 0), zop(h->tmpB, q, 0), h->tmpA, q, 0, one, zero);
     zgemm(gx, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->tmpA, m * q, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->nlog, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
     // X = Q R': site i <- Q, C = R' V^H (q x k)
     qr_factor((int)m, q, h->tmpA, q, 1, h->lw, s);
     qr_form_q((int)m, q, h->tmpA, q, 1, h->lw, M, q, s);
@@ -609,6 +653,7 @@ void truncate_bond(mps_sim* h, int i) {
   HIPCHK(hipMemcpyAsync(h->site[i + 1], h->tmpA, sizeof(cplx) * (size_t)q * n2, hipMemcpyDeviceToDevice, s));
   h->nlog += 1;
   h->nupdates += 1;
+  h->step_upd += 1;
   h->bond[i + 1] = q;
   h->centre = i + 1;
 }
@@ -651,6 +696,7 @@ void run_step(mps_sim* h) {
   std::vector<Op> ops;
   std::vector<int> pos = h->pos;
   h->plan.step_ops(pos, ops);
+  h->step_upd = 0;
   int nu2 = 0, done = 0;
   for (const Op& o : ops) nu2 += (o.kind == 1 || o.kind == 3);
   for (size_t k = 0; k < ops.size(); ++k) {
@@ -671,6 +717,110 @@ void run_step(mps_sim* h) {
     }
   }
   h->steps += 1;
+}
+
+// Truncation-log entries one step appends from the current block order.
+long step_log_entries(mps_sim* h) {
+  std::vector<Op> ops;
+  std::vector<int> pos = h->pos;
+  h->plan.step_ops(pos, ops);
+  long n = 0;
+  for (const Op& o : ops) n += (o.kind == 1) ? 1 : (o.kind == 3 ? o.site_b - o.site : 0);
+  return n;
+}
+
+// One step as a HIP graph: the first step from a given shape signature (bond
+// dimensions, block order, centre) is captured on the handle's stream while
+// the host runs its usual logic, then launched; later steps from the same
+// signature replay it and apply the recorded host-side changes. Only steps
+// whose launches are all plain kernels and device copies qualify (no
+// two-stage eigensolver, which replays a graph of its own; no launch
+// timing); anything else, or a failed capture, runs the step directly.
+void run_step_graphed(mps_sim* h) {
+  if (!h->cfg.graphs || !h->graphs_eligible || !h->stream || h->prof.kind != PROF_OFF) {
+    run_step(h);
+    return;
+  }
+  ensure_log(h, h->nlog + step_log_entries(h));
+  std::vector<int> key(h->bond);
+  key.insert(key.end(), h->pos.begin(), h->pos.end());
+  key.push_back(h->centre);
+  for (auto& g : h->graphs) {
+    if (g.key != key) continue;
+    HIPCHK(hipGraphLaunch(g.exec, h->stream));
+    h->bond = g.bond_after;
+    h->pos = g.pos_after;
+    h->centre = g.centre_after;
+    h->nlog += g.nlog_delta;
+    h->nupdates += g.nupd_delta;
+    h->step_upd = g.step_upd_after;
+    h->steps += 1;
+    h->graph_replays += 1;
+    if (h->progress) h->progress(h->progress_ctx, h->steps - 1, g.nu2, g.nu2);
+    return;
+  }
+  // capture
+  const std::vector<int> bond0 = h->bond, pos0 = h->pos;
+  const int centre0 = h->centre, steps0 = h->steps;
+  const long nlog0 = h->nlog;
+  const uint64_t nupd0 = h->nupdates, supd0 = h->step_upd;
+  auto restore = [&]() {
+    h->bond = bond0; h->pos = pos0; h->centre = centre0; h->steps = steps0;
+    h->nlog = nlog0; h->nupdates = nupd0; h->step_upd = supd0;
+  };
+  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    run_step(h);
+    return;
+  }
+  mps_progress_fn prog = h->progress;
+  h->progress = nullptr;
+  bool ok = true;
+  try {
+    run_step(h);
+  } catch (HipError&) {
+    ok = false;
+  } catch (NoMem&) {
+    ok = false;
+  }
+  h->progress = prog;
+  hipGraph_t graph = nullptr;
+  if (hipStreamEndCapture(h->stream, &graph) != hipSuccess || !graph) ok = false;
+  hipGraphExec_t exec = nullptr;
+  if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {
+    (void)hipGetLastError();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    restore();
+    run_step(h);
+    return;
+  }
+  mps_sim::StepGraph g;
+  g.key = key;
+  g.exec = exec;
+  g.bond_after = h->bond;
+  g.pos_after = h->pos;
+  g.centre_after = h->centre;
+  g.nlog_delta = h->nlog - nlog0;
+  g.nupd_delta = h->nupdates - nupd0;
+  g.step_upd_after = h->step_upd;
+  g.nu2 = (int)g.nlog_delta;
+  const int nu2 = g.nu2;
+  HIPCHK(hipGraphLaunch(exec, h->stream));
+  h->graph_captures += 1;
+  constexpr size_t kMaxGraphs = 8;
+  if (h->graphs.size() < kMaxGraphs) {
+    h->graphs.push_back(std::move(g));
+  } else {
+    // the evicted graph may still be queued or running
+    (void)hipStreamSynchronize(h->stream);
+    auto& slot = h->graphs[h->graph_next];
+    (void)hipGraphExecDestroy(slot.exec);
+    slot = std::move(g);
+    h->graph_next = (h->graph_next + 1) % kMaxGraphs;
+  }
+  if (h->progress) h->progress(h->progress_ctx, h->steps - 1, nu2, nu2);
 }
 
 mps_status check_device(mps_sim* h) {
@@ -766,6 +916,7 @@ void reset_bookkeeping(mps_sim* h) {
   HIPCHK(copy_sync(h, h->dscal, sc, sizeof(sc), hipMemcpyHostToDevice));
   int zero = 0;
   HIPCHK(copy_sync(h, h->lw.flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(copy_sync(h, h->dlogn, &zero, sizeof(int), hipMemcpyHostToDevice));
   h->nlog = 0;
   h->steps = 0;
 }
@@ -849,6 +1000,8 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->env[1] = dalloc<cplx>(h, z.env);
     h->envx = dalloc<cplx>(h, z.envx);
     h->dscal = dalloc<double>(h, 16);
+    h->dlogn = dalloc<int>(h, 1);
+    h->graphs_eligible = !use_two_stage(p.eig_path, z.nmax);
     h->dpartial = dalloc<double>(h, 4096);
     LinalgWork& w = h->lw;
     w.nmax = z.nmax; w.qmax = z.qmax; w.mmax = z.mmax;
@@ -964,7 +1117,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
 mps_status mps_apply_trotter_step(mps_handle h, int32_t nsteps) {
   GUARD(h);
   if (nsteps < 0) return fail(h, MPS_E_INVAL, "nsteps < 0");
-  TRYDEV(h, for (int k = 0; k < nsteps; ++k) run_step(h); HIPCHK(hipGetLastError()));
+  TRYDEV(h, for (int k = 0; k < nsteps; ++k) run_step_graphed(h); HIPCHK(hipGetLastError()));
   return MPS_OK;
 }
 
@@ -1050,6 +1203,7 @@ mps_status mps_fidelity(mps_handle h, double* fidelity, double* log_fidelity) {
 void mps_free(mps_handle h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  release_graphs(h);
   linalg_release(h->lw);
   for (void* p : h->allocations) {
     if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, (void*)h->stream);
@@ -1228,6 +1382,14 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len) {
     re_im[2 * x] = T[flat].real();
     re_im[2 * x + 1] = T[flat].imag();
   }
+  return MPS_OK;
+}
+
+mps_status mps_graph_stats(mps_handle h, int64_t* captures, int64_t* replays) {
+  GUARD(h);
+  if (!captures || !replays) return fail(h, MPS_E_INVAL, "NULL output");
+  *captures = h->graph_captures;
+  *replays = h->graph_replays;
   return MPS_OK;
 }
 

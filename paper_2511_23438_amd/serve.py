@@ -11,6 +11,11 @@ therefore overlap on the device, and the scheduler thread never waits on a
 device: it admits arrivals as memory and slots free up (continuous
 batching, not a FIFO), and retires instances whose workers report back.
 
+Steps of instances whose eigenproblems all take the one-stage solver are
+captured as HIP graphs per shape signature and replayed (the library's
+config field graphs), which removes most per-launch host work for the small
+requests.
+
 Per-step latency is the device time between HIP events recorded on the
 instance's stream before and after its step (the time the step took while
 sharing the GPU with the other instances); queue wait (arrival to
@@ -58,14 +63,15 @@ class Result:
 
 class Server:
     def __init__(self, budget_bytes: int, max_active: int = 16, seed: int = 0,
-                 depth: int = 2):
+                 depth: int = 2, graphs: int = 1):
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.seed = seed
         self.depth = max(1, int(depth))
+        self.graphs = int(graphs)   # steps captured as HIP graphs where they qualify
 
     def _admit(self, req: Request, rid: int, now: float, nbytes: int) -> Active:
-        cfg = mpsim.config_from_instance(req.inst, seed=self.seed + rid)
+        cfg = mpsim.config_from_instance(req.inst, seed=self.seed + rid, graphs=self.graphs)
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             sim = mpsim.Simulation(cfg, stream=stream.cuda_stream)
@@ -183,9 +189,9 @@ class Server:
         }
 
 
-def run_alone(inst: Instance, seed: int) -> dict:
+def run_alone(inst: Instance, seed: int, graphs: int = 1) -> dict:
     """Evolve one instance by itself (reference for the alone-vs-mix check)."""
-    cfg = mpsim.config_from_instance(inst, seed=seed)
+    cfg = mpsim.config_from_instance(inst, seed=seed, graphs=graphs)
     sim = mpsim.Simulation(cfg)
     sim.step(inst.steps)
     obs = sim.measure()

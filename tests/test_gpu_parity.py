@@ -241,10 +241,17 @@ def test_config_4x4_chi16_every_update_replayed(seed):
           "states compared %d (%d with degenerate kept values), max err %.2e" % (
               ncompared, nclustered, terr))
     assert nup == steps * 32
-    # the same program through the step entry point gives the same numbers
+    # the same program through the step entry point: the same updates, and
+    # the same f until the first degenerate cut (from there on the two paths
+    # may keep different, equally valid subspaces: their eigensolver start
+    # vectors are seeded differently)
     sim2 = mpsim.Simulation(cfg)
     sim2.step(steps)
-    assert sim2.measure()["log_fidelity"] == sim.measure()["log_fidelity"]
+    f1, g1 = sim.truncation_log()
+    f2, _ = sim2.truncation_log()
+    assert len(f2) == len(f1)
+    first = int(np.argmax(g1 < 1e-8)) if np.any(g1 < 1e-8) else len(g1)
+    assert np.max(np.abs(f1[:first] - f2[:first])) < 1e-12
     assert sim2.bond_dims() == sim.bond_dims() and sim2.site_blocks() == sim.site_blocks()
 
 
