@@ -232,12 +232,11 @@ def concurrent_from(sites, centre, rows: int, cols: int, chi: int, precision: st
 
 
 def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
-                graphs: int = 1) -> dict:
+                graphs: int = 0) -> dict:
     """The batched workload: `count` independent instances (grids 4x5, 5x5,
     5x6, 6x6 with d 4 and 8, chi in {32, 64, 128, 256}, random J, h, theta0,
     complex64 contractions), each evolved `steps` Trotter steps from its
-    product state, with steps captured as HIP graphs per shape signature when
-    `graphs` is 1. Batched: every instance on its own stream, all stepped
+    product state. Batched: every instance on its own stream, all stepped
     through mps_apply_trotter_step_batched one step at a time (all instances
     enqueued, then one synchronisation per step). One at a time: the first
     `alone_sample` instances (all if 0) evolved alone, one after another; the
@@ -486,8 +485,9 @@ def main() -> int:
                     help="also run the batched workload with this many instances (64 in the "
                          "workload definition)")
     ap.add_argument("--batched-steps", type=int, default=20)
-    ap.add_argument("--batched-graphs", type=int, default=1, choices=[0, 1],
-                    help="capture the batched instances' steps as HIP graphs")
+    ap.add_argument("--batched-graphs", type=int, default=0, choices=[0, 1],
+                    help="graphs config field of the batched instances (the batched entry's "
+                         "worker threads launch directly either way)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload and print its result")
     ap.add_argument("--batched-alone", type=int, default=0,

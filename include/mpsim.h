@@ -119,8 +119,10 @@ typedef struct {
                               launches. Applies only where no step can take the two-stage
                               eigensolver (every Gram side below MPS_EIG2_MIN, eig_path != 2),
                               the stream is not the null stream and no launch class is being
-                              timed; otherwise steps run directly. Captures use the thread-local
-                              capture mode, so other threads' instances are not affected */
+                              timed; otherwise steps run directly. At most one thread of the
+                              process captures at a time (a step that finds another capture in
+                              progress runs directly), and the worker threads of
+                              mps_apply_trotter_step_batched launch directly */
 } mps_config;
 
 typedef struct {

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -26,6 +27,13 @@
 using namespace mpsim;
 
 static thread_local std::string g_tl_error;
+// Steps of the batched entry's worker threads are launched directly, and at
+// most one thread of the process captures a step graph at a time (a step
+// that finds another capture in progress runs directly): captures from many
+// threads at once have ended the process with heap corruption reported by
+// the C library, with no cause found in this library's host code.
+static thread_local bool g_tl_direct_steps = false;
+static std::atomic<int> g_capture_busy{0};
 
 namespace mpsim {
 // Message returned by mps_last_error(NULL) on this thread (calls without a handle).
@@ -737,7 +745,8 @@ long step_log_entries(mps_sim* h) {
 // two-stage eigensolver, which replays a graph of its own; no launch
 // timing); anything else, or a failed capture, runs the step directly.
 void run_step_graphed(mps_sim* h) {
-  if (!h->cfg.graphs || !h->graphs_eligible || !h->stream || h->prof.kind != PROF_OFF) {
+  if (!h->cfg.graphs || !h->graphs_eligible || !h->stream || h->prof.kind != PROF_OFF ||
+      g_tl_direct_steps) {
     run_step(h);
     return;
   }
@@ -759,7 +768,15 @@ void run_step_graphed(mps_sim* h) {
     if (h->progress) h->progress(h->progress_ctx, h->steps - 1, g.nu2, g.nu2);
     return;
   }
-  // capture
+  // capture (one thread of the process at a time)
+  int expected = 0;
+  if (!g_capture_busy.compare_exchange_strong(expected, 1)) {
+    run_step(h);
+    return;
+  }
+  struct CaptureSlot {
+    ~CaptureSlot() { g_capture_busy.store(0); }
+  } slot_guard;
   const std::vector<int> bond0 = h->bond, pos0 = h->pos;
   const int centre0 = h->centre, steps0 = h->steps;
   const long nlog0 = h->nlog;
@@ -1135,6 +1152,7 @@ mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t
   std::vector<mps_status> st(count, MPS_OK);
   auto run = [&](int k) {
     mps_sim* h = hs[k];
+    g_tl_direct_steps = (count > 1);
     if (hipSetDevice(h->device) != hipSuccess) {
       st[k] = fail(h, MPS_E_DEVICE, "hipSetDevice failed");
       return;

@@ -11,10 +11,9 @@ therefore overlap on the device, and the scheduler thread never waits on a
 device: it admits arrivals as memory and slots free up (continuous
 batching, not a FIFO), and retires instances whose workers report back.
 
-Steps of instances whose eigenproblems all take the one-stage solver are
-captured as HIP graphs per shape signature and replayed (the library's
-config field graphs), which removes most per-launch host work for the small
-requests.
+Workers launch their steps directly (the library's step graphs are made
+for one thread at a time; `graphs=1` asks for them anyway, and the library
+then captures on one worker at a time).
 
 Per-step latency is the device time between HIP events recorded on the
 instance's stream before and after its step (the time the step took while
@@ -63,7 +62,7 @@ class Result:
 
 class Server:
     def __init__(self, budget_bytes: int, max_active: int = 16, seed: int = 0,
-                 depth: int = 2, graphs: int = 1):
+                 depth: int = 2, graphs: int = 0):
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.seed = seed
@@ -189,7 +188,7 @@ class Server:
         }
 
 
-def run_alone(inst: Instance, seed: int, graphs: int = 1) -> dict:
+def run_alone(inst: Instance, seed: int, graphs: int = 0) -> dict:
     """Evolve one instance by itself (reference for the alone-vs-mix check)."""
     cfg = mpsim.config_from_instance(inst, seed=seed, graphs=graphs)
     sim = mpsim.Simulation(cfg)
