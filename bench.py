@@ -265,6 +265,8 @@ def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
     stats = [s.graph_stats() for s in sims]
     for s in sims:
         s.free()
+    log("batched set: %d x %d steps in %.1fs (%.3f steps/s)" % (
+        count, steps, t_batched, count * steps / t_batched))
     nalone = count if alone_sample <= 0 else min(alone_sample, count)
     t0 = time.perf_counter()
     same = 0
