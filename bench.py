@@ -232,7 +232,7 @@ def concurrent_from(sites, centre, rows: int, cols: int, chi: int, precision: st
 
 
 def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
-                graphs: int = 0) -> dict:
+                alone_only: bool = False) -> dict:
     """The batched workload: `count` independent instances (grids 4x5, 5x5,
     5x6, 6x6 with d 4 and 8, chi in {32, 64, 128, 256}, random J, h, theta0,
     complex64 contractions), each evolved `steps` Trotter steps from its
@@ -245,11 +245,26 @@ def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
     import torch
     from paper_2511_23438_amd import mpsim, workloads
     insts = workloads.batched(count, seed=seed)
+    if alone_only:
+        t0 = time.perf_counter()
+        per = []
+        for k in range(count):
+            t1 = time.perf_counter()
+            sim = mpsim.Simulation(mpsim.config_from_instance(insts[k], seed=k))
+            sim.step(steps)
+            sim.measure()
+            sim.free()
+            per.append(time.perf_counter() - t1)
+            log("batched set: instance %d alone done, %.1fs" % (k, time.perf_counter() - t0))
+        t_alone = time.perf_counter() - t0
+        return {"instances": count, "steps_each": steps,
+                "alone_seconds": t_alone, "alone_steps_per_s": count * steps / t_alone,
+                "alone_seconds_each": per}
     sims, streams = [], []
     for k, inst in enumerate(insts):
         st = torch.cuda.Stream()
         with torch.cuda.stream(st):
-            sims.append(mpsim.Simulation(mpsim.config_from_instance(inst, seed=k, graphs=graphs),
+            sims.append(mpsim.Simulation(mpsim.config_from_instance(inst, seed=k),
                                          stream=st.cuda_stream))
         streams.append(st)
     torch.cuda.synchronize()
@@ -262,7 +277,6 @@ def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
     obs = [s.measure() for s in sims]
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
-    stats = [s.graph_stats() for s in sims]
     for s in sims:
         s.free()
     log("batched set: %d x %d steps in %.1fs (%.3f steps/s)" % (
@@ -271,7 +285,7 @@ def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
     t0 = time.perf_counter()
     same = 0
     for k in range(nalone):
-        sim = mpsim.Simulation(mpsim.config_from_instance(insts[k], seed=k, graphs=graphs))
+        sim = mpsim.Simulation(mpsim.config_from_instance(insts[k], seed=k))
         sim.step(steps)
         o = sim.measure()
         sim.free()
@@ -283,9 +297,7 @@ def batched_set(count: int, steps: int, seed: int = 2511, alone_sample: int = 0,
     rate_a = nalone * steps / t_alone
     grids = sorted({"%dx%d" % (i.rows, i.cols) for i in insts})
     return {"instances": count, "steps_each": steps, "grids": grids,
-            "chis": sorted({i.chi for i in insts}), "precision": "c64", "graphs": graphs,
-            "graph_captures": int(sum(c for c, _ in stats)),
-            "graph_replays": int(sum(r for _, r in stats)),
+            "chis": sorted({i.chi for i in insts}), "precision": "c64",
             "batched_seconds": t_batched, "batched_steps_per_s": rate_b,
             "alone_instances": nalone, "alone_seconds": t_alone, "alone_steps_per_s": rate_a,
             "speedup": rate_b / rate_a, "bitwise_equal_alone_and_batched": same,
@@ -487,9 +499,8 @@ def main() -> int:
                     help="also run the batched workload with this many instances (64 in the "
                          "workload definition)")
     ap.add_argument("--batched-steps", type=int, default=20)
-    ap.add_argument("--batched-graphs", type=int, default=0, choices=[0, 1],
-                    help="graphs config field of the batched instances (the batched entry's "
-                         "worker threads launch directly either way)")
+    ap.add_argument("--batched-alone-only", action="store_true",
+                    help="with --batched-only: run every instance of the set one at a time only")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload and print its result")
     ap.add_argument("--batched-alone", type=int, default=0,
@@ -522,7 +533,7 @@ def main() -> int:
 
     if args.batched_only:
         res = batched_set(args.batched_set or 64, args.batched_steps,
-                          alone_sample=args.batched_alone, graphs=args.batched_graphs)
+                          alone_sample=args.batched_alone, alone_only=args.batched_alone_only)
         print(json.dumps({"batched_set": res, "wall_s": time.perf_counter() - T_PROC0}),
               flush=True)
         return 0
@@ -675,8 +686,7 @@ def main() -> int:
     if args.batched_set > 0:
         log("batched set: %d instances x %d steps" % (args.batched_set, args.batched_steps))
         out["batched_set"] = batched_set(args.batched_set, args.batched_steps,
-                                         alone_sample=args.batched_alone,
-                                         graphs=args.batched_graphs)
+                                         alone_sample=args.batched_alone)
         log("batched set: %s" % {k: out["batched_set"][k] for k in (
             "batched_steps_per_s", "alone_steps_per_s", "speedup",
             "bitwise_equal_alone_and_batched")})

@@ -111,18 +111,6 @@ typedef struct {
                               the Neel state, round(J tau / 0.02 pi) (at least one when
                               tau > 0) Trotter steps of size tau / count, then
                               exp(-i pi/8 H_Z); their truncations count in F_MPS */
-  int32_t graphs;          /* 0: every step launches its kernels directly. 1: a step is captured
-                              as a HIP graph the first time it starts from a given shape
-                              signature (bond dimensions, block order, orthogonality centre)
-                              and replayed when a later step starts from the same one (up to 8
-                              signatures per handle); results are bit for bit those of direct
-                              launches. Applies only where no step can take the two-stage
-                              eigensolver (every Gram side below MPS_EIG2_MIN, eig_path != 2),
-                              the stream is not the null stream and no launch class is being
-                              timed; otherwise steps run directly. At most one thread of the
-                              process captures at a time (a step that finds another capture in
-                              progress runs directly), and the worker threads of
-                              mps_apply_trotter_step_batched launch directly */
 } mps_config;
 
 typedef struct {
@@ -256,15 +244,9 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len);
  * handle's status (each handle records its own error). */
 mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t nsteps);
 
-/* Steps captured as HIP graphs and steps replayed from them so far (config
- * field graphs). Host only. */
-mps_status mps_graph_stats(mps_handle h, int64_t* captures, int64_t* replays);
-
 /* Optional progress callback: called on the host after each two-site update
  * of mps_apply_trotter_step has been enqueued, with the index of the update
- * within the step and the number of updates per step (once per step, with
- * the index equal to the count, for a step launched as a graph). NULL
- * removes it. */
+ * within the step and the number of updates per step. NULL removes it. */
 typedef void (*mps_progress_fn)(void* ctx, int32_t step, int32_t update, int32_t updates_per_step);
 mps_status mps_set_progress(mps_handle h, mps_progress_fn fn, void* ctx);
 

@@ -8,7 +8,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -27,13 +26,6 @@
 using namespace mpsim;
 
 static thread_local std::string g_tl_error;
-// Steps of the batched entry's worker threads are launched directly, and at
-// most one thread of the process captures a step graph at a time (a step
-// that finds another capture in progress runs directly): captures from many
-// threads at once have ended the process with heap corruption reported by
-// the C library, with no cause found in this library's host code.
-static thread_local bool g_tl_direct_steps = false;
-static std::atomic<int> g_capture_busy{0};
 
 namespace mpsim {
 // Message returned by mps_last_error(NULL) on this thread (calls without a handle).
@@ -83,20 +75,6 @@ struct mps_sim {
 
   int gprec = GEMM_F64;     // arithmetic of the contractions (theta, C, measurement)
 
-  // steps captured as HIP graphs, keyed by the state's shape signature
-  struct StepGraph {
-    std::vector<int> key;   // bonds, block order, centre before the step
-    hipGraphExec_t exec = nullptr;
-    std::vector<int> bond_after, pos_after;
-    int centre_after = 0;
-    long nlog_delta = 0;
-    uint64_t nupd_delta = 0, step_upd_after = 0;
-    int nu2 = 0;
-  };
-  std::vector<StepGraph> graphs;
-  size_t graph_next = 0;
-  bool graphs_eligible = false;  // no step can take the two-stage eigensolver
-  int64_t graph_captures = 0, graph_replays = 0;
   mps_progress_fn progress = nullptr;
   void* progress_ctx = nullptr;
 
@@ -269,15 +247,6 @@ void norm2(mps_sim* h, const cplx* x, long len, int slot) {
   launch_norm2(x, len, h->dpartial, h->dscal + slot, h->stream);
 }
 
-void release_graphs(mps_sim* h) {
-  if (h->graphs.empty()) return;
-  (void)hipStreamSynchronize(h->stream);
-  for (auto& g : h->graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  h->graphs.clear();
-  h->graph_next = 0;
-}
-
 void dev_free(mps_sim* h, void* p) {
   auto it = std::find(h->allocations.begin(), h->allocations.end(), p);
   if (it == h->allocations.end()) return;
@@ -290,15 +259,14 @@ void dev_free(mps_sim* h, void* p) {
   }
 }
 
-// Capacity of the truncation log; growing it moves the log, so captured step
-// graphs (which hold its address) are released.
+// Capacity of the truncation log (growing it moves the log and frees the old
+// buffer).
 void ensure_log(mps_sim* h, long need) {
   if (need <= h->log_cap) return;
   long ncap = std::max(need, 2 * h->log_cap);
   double* nl = dalloc<double>(h, 2 * ncap);
   if (h->nlog > 0)
     HIPCHK(hipMemcpyAsync(nl, h->flog, sizeof(double) * 2 * h->nlog, hipMemcpyDeviceToDevice, h->stream));
-  release_graphs(h);
   if (h->flog) dev_free(h, h->flog);
   h->flog = nl;
   h->log_cap = ncap;
@@ -727,119 +695,6 @@ void run_step(mps_sim* h) {
   h->steps += 1;
 }
 
-// Truncation-log entries one step appends from the current block order.
-long step_log_entries(mps_sim* h) {
-  std::vector<Op> ops;
-  std::vector<int> pos = h->pos;
-  h->plan.step_ops(pos, ops);
-  long n = 0;
-  for (const Op& o : ops) n += (o.kind == 1) ? 1 : (o.kind == 3 ? o.site_b - o.site : 0);
-  return n;
-}
-
-// One step as a HIP graph: the first step from a given shape signature (bond
-// dimensions, block order, centre) is captured on the handle's stream while
-// the host runs its usual logic, then launched; later steps from the same
-// signature replay it and apply the recorded host-side changes. Only steps
-// whose launches are all plain kernels and device copies qualify (no
-// two-stage eigensolver, which replays a graph of its own; no launch
-// timing); anything else, or a failed capture, runs the step directly.
-void run_step_graphed(mps_sim* h) {
-  if (!h->cfg.graphs || !h->graphs_eligible || !h->stream || h->prof.kind != PROF_OFF ||
-      g_tl_direct_steps) {
-    run_step(h);
-    return;
-  }
-  ensure_log(h, h->nlog + step_log_entries(h));
-  std::vector<int> key(h->bond);
-  key.insert(key.end(), h->pos.begin(), h->pos.end());
-  key.push_back(h->centre);
-  for (auto& g : h->graphs) {
-    if (g.key != key) continue;
-    HIPCHK(hipGraphLaunch(g.exec, h->stream));
-    h->bond = g.bond_after;
-    h->pos = g.pos_after;
-    h->centre = g.centre_after;
-    h->nlog += g.nlog_delta;
-    h->nupdates += g.nupd_delta;
-    h->step_upd = g.step_upd_after;
-    h->steps += 1;
-    h->graph_replays += 1;
-    if (h->progress) h->progress(h->progress_ctx, h->steps - 1, g.nu2, g.nu2);
-    return;
-  }
-  // capture (one thread of the process at a time)
-  int expected = 0;
-  if (!g_capture_busy.compare_exchange_strong(expected, 1)) {
-    run_step(h);
-    return;
-  }
-  struct CaptureSlot {
-    ~CaptureSlot() { g_capture_busy.store(0); }
-  } slot_guard;
-  const std::vector<int> bond0 = h->bond, pos0 = h->pos;
-  const int centre0 = h->centre, steps0 = h->steps;
-  const long nlog0 = h->nlog;
-  const uint64_t nupd0 = h->nupdates, supd0 = h->step_upd;
-  auto restore = [&]() {
-    h->bond = bond0; h->pos = pos0; h->centre = centre0; h->steps = steps0;
-    h->nlog = nlog0; h->nupdates = nupd0; h->step_upd = supd0;
-  };
-  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    (void)hipGetLastError();
-    run_step(h);
-    return;
-  }
-  mps_progress_fn prog = h->progress;
-  h->progress = nullptr;
-  bool ok = true;
-  try {
-    run_step(h);
-  } catch (HipError&) {
-    ok = false;
-  } catch (NoMem&) {
-    ok = false;
-  }
-  h->progress = prog;
-  hipGraph_t graph = nullptr;
-  if (hipStreamEndCapture(h->stream, &graph) != hipSuccess || !graph) ok = false;
-  hipGraphExec_t exec = nullptr;
-  if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
-  if (graph) (void)hipGraphDestroy(graph);
-  if (!ok) {
-    (void)hipGetLastError();
-    if (exec) (void)hipGraphExecDestroy(exec);
-    restore();
-    run_step(h);
-    return;
-  }
-  mps_sim::StepGraph g;
-  g.key = key;
-  g.exec = exec;
-  g.bond_after = h->bond;
-  g.pos_after = h->pos;
-  g.centre_after = h->centre;
-  g.nlog_delta = h->nlog - nlog0;
-  g.nupd_delta = h->nupdates - nupd0;
-  g.step_upd_after = h->step_upd;
-  g.nu2 = (int)g.nlog_delta;
-  const int nu2 = g.nu2;
-  HIPCHK(hipGraphLaunch(exec, h->stream));
-  h->graph_captures += 1;
-  constexpr size_t kMaxGraphs = 8;
-  if (h->graphs.size() < kMaxGraphs) {
-    h->graphs.push_back(std::move(g));
-  } else {
-    // the evicted graph may still be queued or running
-    (void)hipStreamSynchronize(h->stream);
-    auto& slot = h->graphs[h->graph_next];
-    (void)hipGraphExecDestroy(slot.exec);
-    slot = std::move(g);
-    h->graph_next = (h->graph_next + 1) % kMaxGraphs;
-  }
-  if (h->progress) h->progress(h->progress_ctx, h->steps - 1, nu2, nu2);
-}
-
 mps_status check_device(mps_sim* h) {
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(h, MPS_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
@@ -1018,7 +873,6 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->envx = dalloc<cplx>(h, z.envx);
     h->dscal = dalloc<double>(h, 16);
     h->dlogn = dalloc<int>(h, 1);
-    h->graphs_eligible = !use_two_stage(p.eig_path, z.nmax);
     h->dpartial = dalloc<double>(h, 4096);
     LinalgWork& w = h->lw;
     w.nmax = z.nmax; w.qmax = z.qmax; w.mmax = z.mmax;
@@ -1134,7 +988,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
 mps_status mps_apply_trotter_step(mps_handle h, int32_t nsteps) {
   GUARD(h);
   if (nsteps < 0) return fail(h, MPS_E_INVAL, "nsteps < 0");
-  TRYDEV(h, for (int k = 0; k < nsteps; ++k) run_step_graphed(h); HIPCHK(hipGetLastError()));
+  TRYDEV(h, for (int k = 0; k < nsteps; ++k) run_step(h); HIPCHK(hipGetLastError()));
   return MPS_OK;
 }
 
@@ -1152,7 +1006,6 @@ mps_status mps_apply_trotter_step_batched(mps_handle* hs, int32_t count, int32_t
   std::vector<mps_status> st(count, MPS_OK);
   auto run = [&](int k) {
     mps_sim* h = hs[k];
-    g_tl_direct_steps = (count > 1);
     if (hipSetDevice(h->device) != hipSuccess) {
       st[k] = fail(h, MPS_E_DEVICE, "hipSetDevice failed");
       return;
@@ -1221,7 +1074,6 @@ mps_status mps_fidelity(mps_handle h, double* fidelity, double* log_fidelity) {
 void mps_free(mps_handle h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
-  release_graphs(h);
   linalg_release(h->lw);
   for (void* p : h->allocations) {
     if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, (void*)h->stream);
@@ -1400,14 +1252,6 @@ mps_status mps_to_statevector(mps_handle h, double* re_im, int64_t len) {
     re_im[2 * x] = T[flat].real();
     re_im[2 * x + 1] = T[flat].imag();
   }
-  return MPS_OK;
-}
-
-mps_status mps_graph_stats(mps_handle h, int64_t* captures, int64_t* replays) {
-  GUARD(h);
-  if (!captures || !replays) return fail(h, MPS_E_INVAL, "NULL output");
-  *captures = h->graph_captures;
-  *replays = h->graph_replays;
   return MPS_OK;
 }
 

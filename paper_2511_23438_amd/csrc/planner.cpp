@@ -42,7 +42,6 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   if (cfg->schedule < 1 || cfg->schedule > 4) { *msg = "schedule must be 1, 2, 3 or 4"; return MPS_E_INVAL; }
   if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
   if (cfg->eig_path < 0 || cfg->eig_path > 2) { *msg = "eig_path must be 0, 1 or 2"; return MPS_E_INVAL; }
-  if (cfg->graphs != 0 && cfg->graphs != 1) { *msg = "graphs must be 0 or 1"; return MPS_E_INVAL; }
   if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
       !std::isfinite(cfg->theta0)) { *msg = "non-finite parameter"; return MPS_E_INVAL; }
   *msg = "";

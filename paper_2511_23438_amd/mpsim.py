@@ -44,7 +44,7 @@ class MpsConfig(C.Structure):
                 ("schedule", C.c_int32), ("periodic", C.c_int32), ("eig_path", C.c_int32),
                 ("J", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("theta0", C.c_double), ("seed", C.c_uint64), ("layers", C.c_int32),
-                ("model", C.c_int32), ("graphs", C.c_int32)]
+                ("model", C.c_int32)]
 
 
 class MpsObs(C.Structure):
@@ -94,7 +94,6 @@ _sig = {
     "mps_apply_trotter_step_batched": (C.c_int, [C.POINTER(H), C.c_int32, C.c_int32]),
     "mps_sync": (C.c_int, [H]),
     "mps_set_progress": (C.c_int, [H, PROGRESS_FN, C.c_void_p]),
-    "mps_graph_stats": (C.c_int, [H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mps_profile": (C.c_int, [H, C.c_int32]),
     "mps_profile_min_work": (C.c_int, [H, C.c_double]),
     "mps_profile_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64),
@@ -124,16 +123,13 @@ def _check(st: int, handle=None) -> None:
 def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
                 dt: float = 0.25, theta0: float = math.pi / 18, order: int = 1,
                 precision: str = "fp64", periodic: bool = True, seed: int = 0,
-                schedule: int = 1, eig_path: int = 0, layers: int = 0,
-                graphs: int = 0) -> MpsConfig:
+                schedule: int = 1, eig_path: int = 0, layers: int = 0) -> MpsConfig:
     """rows x cols grid with half-row blocks, or with layers >= 2 the
     rows x cols x layers cube with one qubit per site (schedule 3 or 4).
     schedule: 1 block pairs with routed wrap pairs, 2 rotating rows, 3 route
-    and return, 4 gate by gate (rank-2 operators and bond truncations).
-    graphs: 1 captures steps as HIP graphs and replays them (see mpsim.h)."""
+    and return, 4 gate by gate (rank-2 operators and bond truncations)."""
     return MpsConfig(rows, cols, chi, PRECISION[precision], order, schedule,
-                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0,
-                     int(graphs))
+                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0)
 
 
 def make_xy_config(rows: int, cols: int, chi: int, g: float = 1.0,
@@ -142,14 +138,13 @@ def make_xy_config(rows: int, cols: int, chi: int, g: float = 1.0,
     """XY-model quench (model 1): rows x cols grid, open boundaries, one qubit
     per site, coupling g, step dt, start state of preparation time tau."""
     return MpsConfig(rows, cols, chi, PRECISION[precision], 2, 3, 0, eig_path, g, 0.0, dt,
-                     tau, seed, 0, 1, 0)
+                     tau, seed, 0, 1)
 
 
-def config_from_instance(inst, seed: int = 0, graphs: int = 0) -> MpsConfig:
+def config_from_instance(inst, seed: int = 0) -> MpsConfig:
     return make_config(inst.rows, inst.cols, inst.chi, inst.J, inst.h, inst.dt,
                        inst.theta0, inst.order, inst.precision, True, seed,
-                       getattr(inst, "schedule", 1), getattr(inst, "eig_path", 0),
-                       graphs=graphs)
+                       getattr(inst, "schedule", 1), getattr(inst, "eig_path", 0))
 
 
 def footprint_bytes(cfg: MpsConfig) -> int:
@@ -256,12 +251,6 @@ class Simulation:
             self.free()
         except Exception:
             pass
-
-    def graph_stats(self) -> tuple[int, int]:
-        """(steps captured as graphs, steps replayed from them)."""
-        c, r = C.c_int64(), C.c_int64()
-        _check(_lib.mps_graph_stats(self.h, C.byref(c), C.byref(r)), self.h)
-        return c.value, r.value
 
     def set_progress(self, fn) -> None:
         """fn(step, update, updates_per_step) after each two-site update is

@@ -11,10 +11,6 @@ therefore overlap on the device, and the scheduler thread never waits on a
 device: it admits arrivals as memory and slots free up (continuous
 batching, not a FIFO), and retires instances whose workers report back.
 
-Workers launch their steps directly (the library's step graphs are made
-for one thread at a time; `graphs=1` asks for them anyway, and the library
-then captures on one worker at a time).
-
 Per-step latency is the device time between HIP events recorded on the
 instance's stream before and after its step (the time the step took while
 sharing the GPU with the other instances); queue wait (arrival to
@@ -62,15 +58,14 @@ class Result:
 
 class Server:
     def __init__(self, budget_bytes: int, max_active: int = 16, seed: int = 0,
-                 depth: int = 2, graphs: int = 0):
+                 depth: int = 2):
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.seed = seed
         self.depth = max(1, int(depth))
-        self.graphs = int(graphs)   # steps captured as HIP graphs where they qualify
 
     def _admit(self, req: Request, rid: int, now: float, nbytes: int) -> Active:
-        cfg = mpsim.config_from_instance(req.inst, seed=self.seed + rid, graphs=self.graphs)
+        cfg = mpsim.config_from_instance(req.inst, seed=self.seed + rid)
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             sim = mpsim.Simulation(cfg, stream=stream.cuda_stream)
@@ -188,9 +183,9 @@ class Server:
         }
 
 
-def run_alone(inst: Instance, seed: int, graphs: int = 0) -> dict:
+def run_alone(inst: Instance, seed: int) -> dict:
     """Evolve one instance by itself (reference for the alone-vs-mix check)."""
-    cfg = mpsim.config_from_instance(inst, seed=seed, graphs=graphs)
+    cfg = mpsim.config_from_instance(inst, seed=seed)
     sim = mpsim.Simulation(cfg)
     sim.step(inst.steps)
     obs = sim.measure()

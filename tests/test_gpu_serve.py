@@ -38,7 +38,7 @@ def test_served_results_equal_alone_and_admission_respects_budget(chis, rows, co
         len(trace), sorted({r.inst.chi for r in trace}), out["peak_active"],
         out["step_latency_ms_p50"], out["step_latency_ms_p99"]))
     for res in out["results"]:
-        alone = serve.run_alone(res.inst, seed=100 + res.rid, graphs=0)   # direct launches
+        alone = serve.run_alone(res.inst, seed=100 + res.rid)
         for k in ("z", "z2", "log_fidelity"):
             assert res.obs[k] == alone[k], (k, res.obs[k], alone[k])
         assert len(res.step_ms) == res.inst.steps
