@@ -215,7 +215,8 @@ def concurrent_from(sites, centre, rows: int, cols: int, chi: int, precision: st
             with torch.cuda.stream(st):
                 sim = mpsim.Simulation(cfg, stream=st.cuda_stream)
             sims.append(sim)
-            sim.set_state(sites, centre)
+            if sites is not None:
+                sim.set_state(sites, centre)
             streams.append(st)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -382,7 +383,8 @@ def state_rate(sites, centre, rows: int, cols: int, chi: int, precision: str, sc
                             schedule=schedule)
     sim = mpsim.Simulation(cfg)
     try:
-        sim.set_state(sites, centre)
+        if sites is not None:       # None: the product state of the config
+            sim.set_state(sites, centre)
         est = None
         done_w = 0
         for w in range(warmup):
@@ -600,21 +602,9 @@ def main() -> int:
             r += args.serve_seconds + 30.0
         return deadline - r
 
-    if sites is None:
-        # product start: the warmup steps grow the bonds
-        cfgp = mpsim.make_config(args.rows, args.cols, args.chi, theta0=args.theta0,
-                                 precision=args.precision, schedule=args.schedule)
-        simp = mpsim.Simulation(cfgp)
-        for _ in range(args.warmup):
-            simp.step(1)
-        simp.sync()
-        bonds = simp.bond_dims()
-        sites = [simp.get_site(p) for p in range(len(bonds) - 1)]
-        simp.free()
-        centre = 0
-        warm = 0
-    else:
-        warm = min(args.warmup, 1)
+    # a saturated random start needs at most one untimed step; from the
+    # product state the warmup steps grow the bonds and all of them run
+    warm = min(args.warmup, 1) if sites is not None else args.warmup
     head = state_rate(sites, centre, args.rows, args.cols, args.chi, args.precision,
                       args.schedule, args.theta0, warm, args.steps, reserve(0.0), args.prof,
                       min_work, reserve_fn=reserve)
@@ -640,7 +630,7 @@ def main() -> int:
                                 4: "gate-by-gate"}[args.schedule],
                    "start": ("seeded random MPS at saturated bonds (seed %d)" % args.seed
                              if args.start == "random" else
-                             "product state + %d untimed steps" % args.warmup)},
+                             "product state + %d untimed steps" % warm)},
         "roofline": roof,
         "observables": head["observables"],
         "budget_s": args.budget,
