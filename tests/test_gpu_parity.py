@@ -255,6 +255,50 @@ def test_config_4x4_chi16_every_update_replayed(seed):
     assert sim2.bond_dims() == sim.bond_dims() and sim2.site_blocks() == sim.site_blocks()
 
 
+def test_config_5x6_c64_every_update_replayed():
+    """The 5x6, d = 8 workload with complex64 contractions (float64
+    truncation) at chi = 64, 20 steps from the product state, driven op by op:
+    before every two-site update the GPU's own state is loaded into the
+    float64 oracle, which applies the same update; every f (unique even at
+    degenerate cuts) is compared within 1e-5 relative, and after every step
+    the oracle's float64 measurement of the GPU's state against the
+    library's measurement (complex64 contractions) within 1e-5. Errors
+    printed."""
+    R, C, chi, steps = 5, 6, 64, 20
+    cfg = mpsim.make_config(R, C, chi, theta0=math.pi / 18, precision="c64")
+    sim = mpsim.Simulation(cfg)
+    ops = mpsim.schedule_dump(cfg, steps)
+    per_step = len(ops) // steps
+    ferr = oerr = 0.0
+    nup = 0
+    for s_ in range(steps):
+        recs = ops[s_ * per_step:(s_ + 1) * per_step]
+        u2 = [k for k, r in enumerate(recs) if r[0] == 1]
+        for k, rec in enumerate(recs):
+            if rec[0] == 2:
+                sim.apply_single_site(int(rec[1]), int(rec[2]))
+                continue
+            site, swap, gate = int(rec[1]), int(rec[2]), int(rec[3])
+            later = [j for j in u2 if j > k]
+            nxt = int(recs[later[0]][1]) if later else -1
+            ora = _oracle_from_gpu(sim, R, C, chi)
+            f_ora = ora.apply_u2(site, bool(swap), bool(gate))
+            sim.apply_two_site(site, bool(swap), bool(gate), nxt)
+            nup += 1
+            f_gpu = sim.truncation_log()[0][-1]
+            e = abs(f_gpu - f_ora) / f_ora
+            ferr = max(ferr, e)
+            assert e < 1e-5, (s_, k, f_gpu, f_ora)
+        o = sim.measure()
+        ref = _oracle_from_gpu(sim, R, C, chi).measure()
+        for key in ("z", "z2"):
+            oerr = max(oerr, abs(o[key] - ref[key]))
+            assert abs(o[key] - ref[key]) < 1e-5, (s_, key, o[key], ref[key])
+    print("5x6 chi64 c64: %d updates, max f rel err %.2e, max observable err %.2e" % (
+        nup, ferr, oerr))
+    assert nup == steps * (11 * R - 12)
+
+
 def test_estimators_match_oracle():
     """Rescaled estimators of the library against the oracle's functions
     applied to the oracle's own run (symmetry-free truncating start state)."""
