@@ -99,6 +99,8 @@ _sig = {
     "mps_profile_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
     "mps_last_error": (C.c_char_p, [H]),
+    "mps_measure_static": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -338,6 +340,20 @@ class Simulation:
         _check(_lib.mps_to_statevector(self.h, arr.ctypes.data_as(C.POINTER(C.c_double)), ln),
                self.h)
         return arr.view(np.complex128)
+
+
+def measure_static(bonds: Sequence[int], dims: Sequence[int], site_ptrs: Sequence[int],
+                   stream: int, out_ptr: int) -> None:
+    """mps_measure_static: the measurement of an MPS held in device memory
+    (site_ptrs: device addresses of the row-major (b d) x b' complex128
+    sites) with no allocation; out_ptr: device address of 3 doubles
+    (<psi|psi>, <Z_tot>/n, <Z_tot^2>/n^2). Asynchronous on `stream`."""
+    n = len(dims)
+    bb = (C.c_int32 * (n + 1))(*[int(b) for b in bonds])
+    dd = (C.c_int32 * n)(*[int(d) for d in dims])
+    pp = (C.c_void_p * n)(*[int(p) for p in site_ptrs])
+    _check(_lib.mps_measure_static(n, bb, dd, pp, C.c_void_p(int(stream)),
+                                   C.c_void_p(int(out_ptr))))
 
 
 def apply_batched(sims: Sequence[Simulation], nsteps: int = 1) -> None:

@@ -16,14 +16,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "mpsim.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mps_[a-z_0-9]+)\s*\(", txt)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(mps_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_symbols_exported():
     names = _declared()
-    assert len(names) >= 18
+    assert len(names) >= 18 and "mps_measure_static" in names
     for n in names:
         assert hasattr(mpsim._lib, n), n
         assert n in mpsim.EXPORTED, n

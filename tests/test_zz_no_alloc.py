@@ -13,9 +13,6 @@ from paper_2511_23438_amd import mpsim, workloads
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
 _lib = mpsim._lib
-_lib.mps_measure_static.restype = C.c_int
-_lib.mps_measure_static.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                    C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]
 
 
 def _measure_static(sites_dev, bonds, dims, out, stream):
