@@ -801,13 +801,15 @@ __global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx*
   }
   if (i < QR_NB) ts[i] = (i < ib) ? tau[i] : make_double2(0.0, 0.0);
   __syncthreads();
+  // row i of T: T[i][j] = -tau_j sum_{l = i .. j-1} T[i][l] S[l][j]; the
+  // entries l < i of the row are exact zeros, so the sum runs over every
+  // l < j without a lane-dependent bound (no branches in the unrolled loop)
   cplx row[QR_NB];
 #pragma unroll
   for (int j = 0; j < QR_NB; ++j) {
     cplx acc = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int l = 0; l < j; ++l)
-      if (l >= i) acc = cadd(acc, cmul(row[l], Ss[l][j]));
+    for (int l = 0; l < j; ++l) acc = cadd(acc, cmul(row[l], Ss[l][j]));
     cplx v = make_double2(0.0, 0.0);
     if (i < ib && j < ib) {
       if (j == i) v = ts[j];
