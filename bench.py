@@ -432,7 +432,7 @@ def state_rate(sites, centre, rows: int, cols: int, chi: int, precision: str, sc
                 "steps_per_s": k / elapsed, "ms_per_step": 1e3 * elapsed / k,
                 "prof": {"kernel": prof, "ms": ms_k, "launches": launches, "work": work},
                 "observables": {"z": obs["z"], "z2": obs["z2"], "fidelity": obs["fidelity"],
-                                "norm": obs["norm"]}}
+                                "norm": obs["norm"], "eig_suspect": obs["eig_suspect"]}}
     finally:
         sim.free()
 

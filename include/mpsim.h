@@ -111,11 +111,22 @@ typedef struct {
                               the Neel state, round(J tau / 0.02 pi) (at least one when
                               tau > 0) Trotter steps of size tau / count, then
                               exp(-i pi/8 H_Z); their truncations count in F_MPS */
+  int32_t eig_batch;       /* eigenvectors per band inverse-iteration launch of the two-stage
+                              eigensolver: 0 means 1024, else 1..1024. That path keeps, per
+                              vector in a launch, its band LU factors (99 complex per Gram
+                              row: 26.6 GB for 1024 vectors at a Gram side of 16384, the
+                              largest workspace of an instance); a smaller batch bounds
+                              them at eig_batch * n * 99 * 16 bytes for more, narrower
+                              launches. Results do not depend on it */
 } mps_config;
 
 typedef struct {
   int32_t step;            /* Trotter steps applied since init */
-  int32_t reserved;
+  int32_t eig_suspect;     /* truncations since init (or mps_set_state) whose kept weight |C|^2
+                              and the sum of the kept Gram eigenvalues (bisection) differ by more
+                              than 1e-9 |M|^2 (1e-5 with reduced-precision contractions): the
+                              two agree whenever the eigenvectors span the top-q eigenspace, so
+                              a nonzero count flags eigenvectors that did not converge */
   double z;                /* <Z_tot>_MPS, eq. "Z_tot" on the normalised MPS (XY model: the
                               conserved charge density <sum_j Z_j> / n) */
   double z2;               /* <Z_tot^2>_MPS, eq. "z2_tot" (XY model: the signal X2_tot of
@@ -277,6 +288,16 @@ mps_status mps_profile_min_work(mps_handle h, double min_work);
 /* Accumulated device time (ms), number of timed launches and their
  * algorithmic work (bytes or flops, per the class). Synchronises. */
 mps_status mps_profile_read(mps_handle h, double* total_ms, int64_t* launches, double* work);
+
+/* Operand extent checks (diagnostic, process-wide, off by default). While
+ * enabled (enable != 0), every complex GEMM, reflector extraction, QR and
+ * eigensolver launch is preceded by a host-side check that each operand's
+ * first and last accessed element lie inside the one device buffer of the
+ * library that holds its base address (the caller's site buffers count
+ * during mps_measure_static). A failing check launches nothing and the call
+ * returns MPS_E_DEVICE with a message naming the operand; the handle is then
+ * failed. Host only; always MPS_OK. */
+mps_status mps_debug_check_bounds(int32_t enable);
 
 /* Last error message of the handle (thread-local message if h == NULL). */
 const char* mps_last_error(mps_handle h);

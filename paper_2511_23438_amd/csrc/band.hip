@@ -763,14 +763,22 @@ __global__ __launch_bounds__(64) void k_band_invit(int n, const cplx* Br, int q,
   }
 }
 
-// vectors per inverse-iteration launch (bounds the U workspace)
-int band_invit_batch(int q) { return std::min(q, 1024); }
+// vectors per inverse-iteration launch (bounds the U workspace); every
+// vector's iteration depends only on its own index, so the batching does not
+// change the results
+static int band_invit_batch(int q, int batch) { return std::max(1, std::min(q, batch)); }
 
-long band_invit_work_elems(long n, int q) { return (long)band_invit_batch(q) * n * (URW + LRW); }
+long band_invit_work_elems(long n, int q, int batch) {
+  return (long)band_invit_batch(q, batch) * n * (URW + LRW);
+}
 
 void band_invit(int n, const cplx* Br, int q, int lam_off, LinalgWork& w, cplx* X, long ldx,
                 uint64_t seed, hipStream_t s) {
-  const int bs = band_invit_batch(q);
+  const int bs = band_invit_batch(q, w.invit_batch);
+  require_strided(Br, ABW, 1, 0, 0, n, ABW, "band inverse iteration: band rows");
+  require_strided(w.Ubuf, (long)n * (URW + LRW), 1, 0, 0, bs, (long)n * (URW + LRW),
+                  "band inverse iteration: LU rows");
+  require_strided(X, ldx, 1, 0, 0, n, q, "band inverse iteration: vectors");
   for (int v0 = 0; v0 < q; v0 += bs) {
     const int cnt = std::min(bs, q - v0);
     hipLaunchKernelGGL(k_band_invit, dim3(cnt), dim3(64), 0, s, n, Br, q, (const double*)w.lam,
@@ -780,6 +788,11 @@ void band_invit(int n, const cplx* Br, int q, int lam_off, LinalgWork& w, cplx* 
 
 void heev_top_2stage(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
                      uint64_t seed, hipStream_t s) {
+  require_strided(G, 1, ldg, 0, 0, n, n, "two-stage eigensolver: Gram matrix");
+  require_strided(U, ldu, 1, 0, 0, n, q, "two-stage eigensolver: eigenvectors");
+  require_strided(Xtmp, q, 1, 0, 0, n, q, "two-stage eigensolver: work vectors");
+  require_strided(w.Ab, ABW, 1, 0, 0, n, ABW, "two-stage eigensolver: band");
+  require_strided(w.Br, ABW, 1, 0, 0, n, ABW, "two-stage eigensolver: band rows");
   he2hb_lower(n, G, ldg, w, s);
   const long tot = (long)n * ABW;
   const int bl = (int)std::min<long>((tot + 255) / 256, 4096);

@@ -5,6 +5,29 @@
 
 typedef double2 cplx;  // interleaved complex double (re, im)
 
+#include <string>
+
+namespace mpsim {
+// Host-side extent checks of launch operands. Every device buffer of the
+// library is registered (base address, bytes); while checks are switched on
+// (mps_debug_check_bounds), a launcher whose operand would reach outside the
+// buffer that holds its base address throws BoundsError instead of
+// launching. Process-wide; off by default.
+struct BoundsError {
+  std::string msg;
+};
+void bounds_register(const void* p, size_t bytes);
+// registers p unless a buffer with that base is registered; true if added
+bool bounds_register_new(const void* p, size_t bytes);
+void bounds_unregister(const void* p);
+bool bounds_checking();
+void bounds_set_checking(bool on);
+// Elements lo..hi (inclusive, of `elem` bytes, relative to p) must lie in
+// one registered buffer. No-op while checks are off, for p == NULL or for
+// hi < lo (nothing accessed).
+void bounds_require(const void* p, long lo, long hi, size_t elem, const char* what);
+}  // namespace mpsim
+
 __host__ __device__ inline cplx cmake(double r, double i) { return make_double2(r, i); }
 __host__ __device__ inline cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }

@@ -773,8 +773,49 @@ static void transpose_problem(ZGemm& g) {
   std::swap(g.lower_only, g.upper_only);
 }
 
+// Operand extents of a product (host side, while operand checks are on):
+// element (i, k), i < rows, k < cols, of o over `batch` batches.
+static void require_op(const ZOp& o, long rows, long cols, int batch, const char* what) {
+  if (rows <= 0 || cols <= 0) return;
+  const long last = o.trans ? (cols - 1) * o.ld + (rows - 1) : (rows - 1) * o.ld + (cols - 1);
+  const long bs = (long)(batch - 1) * o.stride;
+  bounds_require(o.p, std::min(0L, bs), last + std::max(0L, bs), sizeof(cplx), what);
+}
+
+static void require_gemm_operands(const ZGemm& g, const cplx* partial, long partial_elems) {
+  const long kc = g.kcat > 0 ? g.kcat : g.K;
+  if (g.K > 0) {
+    if (g.herm_a) {
+      const long last = (long)(g.M - 1) * g.A.ld + (g.M - 1);
+      const long bs = (long)(g.batch - 1) * g.A.stride;
+      bounds_require(g.A.p, std::min(0L, bs), last + std::max(0L, bs), sizeof(cplx),
+                     "product: Hermitian A");
+    } else {
+      require_op(g.A, g.M, kc, g.batch, "product: A");
+      if (g.kcat > 0) require_op(g.A2, g.M, g.K - g.kcat, g.batch, "product: A2");
+    }
+    require_op(g.B, kc, g.N, g.batch, "product: B");
+    if (g.kcat > 0 && !g.herm_a) require_op(g.B2, g.K - g.kcat, g.N, g.batch, "product: B2");
+  }
+  long clast;
+  if (g.epi == EPI_THETA && g.swap)
+    clast = ((long)(g.M - 1) / g.d1 * g.d2 + (g.N - 1) / g.b2) * ((long)g.d1 * g.b2) +
+            (long)(g.d1 - 1) * g.b2 + (g.b2 - 1);
+  else if (g.epi == EPI_THETA || !g.transC)
+    clast = (long)(g.M - 1) * g.ldc + (g.N - 1);
+  else
+    clast = (long)(g.N - 1) * g.ldc + (g.M - 1);
+  const long cs = (long)(g.batch - 1) * g.strideC;
+  bounds_require(g.C, std::min(0L, cs), clast + std::max(0L, cs), sizeof(cplx), "product: C");
+  if (g.epi == EPI_THETA && g.phase)
+    bounds_require(g.phase, 0, (long)g.d1 * g.d2 - 1, sizeof(cplx), "product: phase table");
+  if (partial && partial_elems > 0)
+    bounds_require(partial, 0, partial_elems - 1, sizeof(cplx), "product: split-K partials");
+}
+
 void zgemm(const ZGemm& g0, cplx* partial, long partial_elems, hipStream_t s, Prof* prof) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return;
+  if (bounds_checking()) require_gemm_operands(g0, partial, partial_elems);
   ZGemm g = g0;
   if (g.herm_a) {
     // only the plain float64 product with a row-major result

@@ -63,6 +63,7 @@ struct LinalgWork {
   cplx* Ab = nullptr;       // band, nmax x (2*TRD_NB + 1), bulge-chased in place
   cplx* Br = nullptr;       // row-major copy of the band before chasing
   cplx* Ubuf = nullptr;     // inverse-iteration U rows, band_invit_work_elems()
+  int invit_batch = 1024;   // vectors per band inverse-iteration launch
   // bulge-chasing launch sequences captured as HIP graphs, per (n, band)
   struct HbGraph {
     int n = -1;
@@ -75,6 +76,12 @@ struct LinalgWork {
   hipStream_t cap_stream = nullptr;  // private stream used only for capture
   Prof* prof = nullptr;     // optional launch timing
 };
+
+// Elements (r, c), r0 <= r < r0 + rows, c0 <= c < c0 + cols, of a strided
+// matrix (element (r, c) at A[r*rs + c*cs], rs, cs >= 0) must lie in one
+// buffer of the library (while operand checks are on; throws BoundsError).
+void require_strided(const void* A, long rs, long cs, long r0, long c0, long rows, long cols,
+                     const char* what);
 
 // Reduce Hermitian A (n x n, column-major, lower triangle referenced) to real
 // symmetric tridiagonal form A = Q T Q^H. T goes to w.d / w.e, reflectors
@@ -122,7 +129,8 @@ void apply_block_reflector(int mrows, int ncols, int ib, const cplx* T, int tcon
 // Same contract as heev_top.
 void heev_top_2stage(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
                      uint64_t seed, hipStream_t s);
-long band_invit_work_elems(long n, int q);
+// Elements of w.Ubuf for `q` vectors of side n, `batch` vectors per launch.
+long band_invit_work_elems(long n, int q, int batch);
 // Destroys the captured graphs and the capture stream of `w`.
 void linalg_release(LinalgWork& w);
 constexpr int BAND_W = 2 * TRD_NB + 1;

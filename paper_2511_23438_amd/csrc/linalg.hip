@@ -731,8 +731,17 @@ __global__ void k_extract_v(const cplx* A, long rs, long cs, int row0, int col0,
   }
 }
 
+void require_strided(const void* A, long rs, long cs, long r0, long c0, long rows, long cols,
+                     const char* what) {
+  if (rows <= 0 || cols <= 0) return;
+  bounds_require(A, r0 * rs + c0 * cs, (r0 + rows - 1) * rs + (c0 + cols - 1) * cs, sizeof(cplx),
+                 what);
+}
+
 void extract_v(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib, cplx* V,
                long ldv, hipStream_t s) {
+  require_strided(A, rs, cs, row0, col0, mrows, ib, "reflectors: source");
+  require_strided(V, 1, ldv, 0, 0, mrows, ib, "reflectors: V");
   const long tv = (long)mrows * ib;
   const int bl = (int)std::min<long>((tv + 255) / 256, 2048);
   hipLaunchKernelGGL(k_extract_v, dim3(std::max(bl, 1)), dim3(256), 0, s, A, rs, cs, row0, col0, mrows,
@@ -832,6 +841,9 @@ __global__ __launch_bounds__(64) void k_larft(int ib, const cplx* S, const cplx*
 void block_reflector(const cplx* A, long rs, long cs, int row0, int col0, int mrows, int ib,
                             const cplx* tau, cplx* T, LinalgWork& w, hipStream_t s) {
   const long ldv = w.vmax;
+  require_strided(A, rs, cs, row0, col0, mrows, ib, "block reflector: source");
+  require_strided(w.V, 1, ldv, 0, 0, mrows, ib, "block reflector: V");
+  require_strided(T, 64, 1, 0, 0, ib, ib, "block reflector: T");
   long total = (long)mrows * ib;
   int blocks = (int)std::min<long>((total + 255) / 256, 2048);
   hipLaunchKernelGGL(k_extract_v, dim3(blocks), dim3(256), 0, s, A, rs, cs, row0, col0, mrows, ib,
@@ -1042,6 +1054,15 @@ __global__ __launch_bounds__(256) void k_qr_col(int m, cplx* A, long rs, long cs
 
 void qr_factor(int m, int k, cplx* A, long rs, long cs, LinalgWork& w, hipStream_t s) {
   const int kmin = std::min(m, k);
+  require_strided(A, rs, cs, 0, 0, m, k, "QR: matrix");
+  if (kmin > 0) {
+    // the two (pivot row, partials) halves of the column steps
+    const long nparts = std::max(1, ceil_div(m, 256));
+    require_strided(w.tpart, 1, 0, 0, 0, w.tpart_elems, 1, "QR: column-step partials");
+    if (2 * (QR_NB + nparts * QR_NB) > w.tpart_elems)
+      throw BoundsError{"QR: column-step partials need " + std::to_string(2 * (QR_NB + nparts * QR_NB)) +
+                        " elements, the buffer holds " + std::to_string(w.tpart_elems)};
+  }
   // two buffers of (pivot row copy, partial sums), alternating between
   // column steps
   cplx* pivA = w.tpart;
@@ -1130,6 +1151,10 @@ void hetrd_backtransform(int n, const cplx* A, long lda, int q, cplx* X, long ld
 
 void heev_top(int n, cplx* G, long ldg, int q, cplx* U, long ldu, cplx* Xtmp, LinalgWork& w,
               uint64_t seed, hipStream_t s) {
+  require_strided(G, 1, ldg, 0, 0, n, n, "eigensolver: Gram matrix");
+  require_strided(U, ldu, 1, 0, 0, n, q, "eigensolver: eigenvectors");
+  require_strided(Xtmp, q, 1, 0, 0, n, q, "eigensolver: work vectors");
+  require_strided(w.iwork, 1, 0, 0, 0, 6L * n * q / 2, 1, "eigensolver: inverse-iteration work");
   hetrd_lower(n, G, ldg, w, s);
   const int extra = (q < n) ? 1 : 0;
   tridiag_eigvals(n, n - q - extra, q + extra, w, s);

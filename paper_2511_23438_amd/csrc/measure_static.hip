@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/mpsim_static.h"
 #include "common.h"
@@ -40,6 +41,7 @@ hipError_t scratch_address(int dev, void** out) {
     hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return e;
     g_scratch[dev] = p;
+    bounds_register(p, (size_t)MPS_MEASURE_STATIC_BYTES);
   }
   *out = g_scratch[dev];
   return hipSuccess;
@@ -120,6 +122,19 @@ extern "C" mps_status mps_measure_static(int32_t nsites, const int32_t* bonds, c
   double* zs = (double*)(b8 + 2 * env_b + x_b);
   hipStream_t s = (hipStream_t)hip_stream;
   const cplx one = make_double2(1, 0), zero = make_double2(0, 0);
+  // with operand checks on, the caller's sites count as buffers for this call
+  std::vector<const void*> added;
+  if (bounds_checking())
+    for (int p = 0; p < nsites; ++p)
+      if (bounds_register_new(sites[p], sizeof(cplx) * (size_t)bonds[p] * dims[p] * bonds[p + 1]))
+        added.push_back(sites[p]);
+  struct Unregister {
+    std::vector<const void*>& v;
+    ~Unregister() {
+      for (const void* p : v) bounds_unregister(p);
+    }
+  } unreg{added};
+  try {
   // every buffer region read below is written first in this call: the
   // environment starts as {1, 0, 0}, the GEMMs overwrite (beta = 0)
   long zoff = 0;
@@ -154,6 +169,9 @@ extern "C" mps_status mps_measure_static(int32_t nsites, const int32_t* bonds, c
     zoff += d;
   }
   hipLaunchKernelGGL(k_meas_finish, dim3(1), dim3(1), 0, s, (const cplx*)env[cur], (double)n, out_dev);
+  } catch (BoundsError& be) {
+    return fail_static(MPS_E_DEVICE, "mps_measure_static: operand out of bounds, not launched: " + be.msg);
+  }
   e = hipGetLastError();
   if (e != hipSuccess)
     return fail_static(MPS_E_DEVICE, std::string("mps_measure_static: launch: ") + hipGetErrorString(e));

@@ -26,10 +26,12 @@ void launch_trace_real(const cplx* G, long n, long ldg, double* dst, hipStream_t
 // dst[slot] = sum |x|^2 over len entries (deterministic two-pass reduction).
 void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStream_t s);
 // Truncation bookkeeping: f = sc[3]/sc[2], sc[0] += log f, sc[4] = 1/sqrt(sc[3]),
-// log entry *count gets (f, gap) and *count is incremented; gap from the
-// ascending eigenvalues lam.
+// log entry count[0] gets (f, gap) and count[0] is incremented; gap from the
+// ascending eigenvalues lam (lam[extra .. extra+q-1]: the kept ones);
+// count[1] is incremented when sc[3] and the kept eigenvalues' sum differ by
+// more than tol * sc[2].
 void launch_trunc_finalize(double* sc, double* flog, int* count, const double* lam, int q, int extra,
-                           int* flag, hipStream_t s);
+                           int* flag, double tol, hipStream_t s);
 // x *= sc[4]
 void launch_scale_by(cplx* x, long len, const double* sc, hipStream_t s);
 // dst (cols x rows, ld ldd) = conj(src)^T, src rows x cols (ld lds)

@@ -228,10 +228,21 @@ void launch_norm2(const cplx* x, long len, double* partial, double* dst, hipStre
   hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(256), 0, s, (const double*)partial, NORM_BLOCKS, dst);
 }
 
-__global__ void k_trunc_finalize(double* sc, double* flog, int* count, const double* lam, int q, int extra,
-                                 int* flag) {
-  const int idx = *count;  // the log position is kept on the device (graph replays reuse launches)
-  *count = idx + 1;
+// One wave. count[0]: next log position (kept on the device); count[1]:
+// truncations whose kept weight |C|^2 = trace(U^H G U) differs from the sum
+// of the top q eigenvalues of G (bisection) by more than tol |M|^2 -- the
+// two agree whenever U spans the top-q eigenspace, so a difference means
+// the eigenvectors did not converge.
+__global__ __launch_bounds__(64) void k_trunc_finalize(double* sc, double* flog, int* count,
+                                                       const double* lam, int q, int extra, int* flag,
+                                                       double tol) {
+  const int t = threadIdx.x;
+  double part = 0.0;
+  for (int k = extra + t; k < q + extra; k += 64) part += lam[k];
+  const double lsum = wave_sum(part);
+  if (t != 0) return;
+  const int idx = count[0];
+  count[0] = idx + 1;
   const double nM = sc[2], nC = sc[3];
   const double f = nC / nM;
   double gap = INFINITY;
@@ -240,6 +251,7 @@ __global__ void k_trunc_finalize(double* sc, double* flog, int* count, const dou
     if (lmax > 0.0) gap = (sqrt(lq) - sqrt(lq1)) / sqrt(lmax);
   }
   if (!(f > 0.0) || !isfinite(f) || !(nC > 0.0)) *flag = 1;
+  if (!(fabs(nC - lsum) <= tol * nM)) count[1] += 1;
   sc[0] += log(f);
   sc[1] = fmin(sc[1], gap);
   sc[4] = 1.0 / sqrt(nC);
@@ -248,8 +260,9 @@ __global__ void k_trunc_finalize(double* sc, double* flog, int* count, const dou
 }
 
 void launch_trunc_finalize(double* sc, double* flog, int* count, const double* lam, int q, int extra,
-                           int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_trunc_finalize, dim3(1), dim3(1), 0, s, sc, flog, count, lam, q, extra, flag);
+                           int* flag, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_trunc_finalize, dim3(1), dim3(64), 0, s, sc, flog, count, lam, q, extra, flag,
+                     tol);
 }
 
 __global__ void k_scale_by(cplx* x, long len, const double* sc) {

@@ -59,7 +59,7 @@ struct mps_sim {
   double* dscal = nullptr;   // [0] logF [1] min gap [2] |M|^2 [3] |C|^2 [4] 1/|C|
   double* dpartial = nullptr;
   double* flog = nullptr;
-  int* dlogn = nullptr;     // device copy of nlog: the next log position
+  int* dlogn = nullptr;     // [0] next log position (device copy of nlog), [1] suspect truncations
   long log_cap = 0, nlog = 0;
   LinalgWork lw;
   Prof prof;
@@ -111,6 +111,7 @@ void* dev_alloc(mps_sim* h, size_t bytes) {
     }
   }
   h->allocations.push_back(p);
+  bounds_register(p, bytes);
   return p;
 }
 
@@ -122,12 +123,13 @@ T* dalloc(mps_sim* h, long count) {
 struct Sizes {
   long site_max = 0, sites_total = 0, theta = 0, gram = 0, nmax = 1, qmax = 1, mmax = 1,
        colmax = 1, tmp = 0, env = 0, envx = 0;
-  int eig_path = 0;
+  int eig_path = 0, eig_batch = 1024;
 };
 
 Sizes plan_sizes(const Plan& p) {
   Sizes z;
   z.eig_path = p.eig_path;
+  z.eig_batch = p.eig_batch;
   const long D = p.dmax;
   for (int s = 0; s < p.N; ++s) {
     long e = (long)p.xcap[s] * D * p.xcap[s + 1];
@@ -203,7 +205,7 @@ LwSizes lw_sizes(const Sizes& z) {
     l.T1 = (z.nmax / TRD_NB + 2) * 4096;
     l.X2 = z.nmax * 64;
     l.band = z.nmax * BAND_W;
-    l.ubuf = band_invit_work_elems(z.nmax, (int)z.qmax);
+    l.ubuf = band_invit_work_elems(z.nmax, (int)z.qmax, z.eig_batch);
     l.acc = he2hb_acc_elems(z.nmax);
   }
   return l;
@@ -243,6 +245,11 @@ mps_status fail(mps_sim* h, mps_status st, const std::string& msg) {
 // ---------------------------------------------------------------------------
 // building blocks
 
+// Bound on | |C|^2 - sum of the kept eigenvalues | / |M|^2 above which a
+// truncation counts as suspect: float64 contractions agree to ~1e-13, the
+// reduced-precision ones to their own rounding (~1e-7).
+double eig_check_tol(const mps_sim* h) { return h->gprec == GEMM_F64 ? 1e-9 : 1e-5; }
+
 void norm2(mps_sim* h, const cplx* x, long len, int slot) {
   launch_norm2(x, len, h->dpartial, h->dscal + slot, h->stream);
 }
@@ -251,6 +258,7 @@ void dev_free(mps_sim* h, void* p) {
   auto it = std::find(h->allocations.begin(), h->allocations.end(), p);
   if (it == h->allocations.end()) return;
   h->allocations.erase(it);
+  bounds_unregister(p);
   if (h->has_alloc) {
     h->alloc.free(h->alloc.ctx, p, (void*)h->stream);   // stream-ordered
   } else {
@@ -445,7 +453,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     zgemm(gc, nullptr, 0, s, &h->prof);
     launch_unpermute_rows(h->tmpB, A, (int)b0, d, q, s);
     norm2(h, h->theta, (long)q * ldb, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, eig_check_tol(h), s);
     launch_scale_by(h->theta, (long)q * ldb, h->dscal, s);
     HIPCHK(hipMemcpyAsync(B, h->theta, sizeof(cplx) * (size_t)q * ldb, hipMemcpyDeviceToDevice, s));
     h->centre = i + 1;
@@ -468,7 +476,7 @@ bool two_site_factored(mps_sim* h, int i, int gate, bool left, int q, uint64_t s
     // site i+1 = V^H (q x d b2)
     launch_conj_transpose(h->tmpB, (int)kg, q, q, B, kg, s);
     norm2(h, h->theta, b0 * d * q, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, eig_check_tol(h), s);
     launch_scale_by(h->theta, b0 * d * q, h->dscal, s);
     HIPCHK(hipMemcpyAsync(A, h->theta, sizeof(cplx) * (size_t)(b0 * d * q), hipMemcpyDeviceToDevice, s));
     h->centre = i;
@@ -535,7 +543,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i + 1], (long)q * no, 3);
     ensure_log(h, h->nlog + 1);
-    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, eig_check_tol(h), s);
     launch_scale_by(h->site[i + 1], (long)q * no, h->dscal, s);
     h->centre = i + 1;
   } else {
@@ -555,7 +563,7 @@ void two_site(mps_sim* h, int i, int swap, int gate, int next_site) {
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->site[i], mo * q, 3);
     ensure_log(h, h->nlog + 1);
-    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, eig_check_tol(h), s);
     launch_scale_by(h->site[i], mo * q, h->dscal, s);
     h->centre = i;
   }
@@ -598,7 +606,7 @@ void truncate_bond(mps_sim* h, int i) {
     ZGemm gc = zgemm_args(q, k, kg, zop(h->tmpB, q, 1, 1), zop(M, k, 0), h->theta, k, 0, one, zero);
     zgemm(gc, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->theta, (long)q * k, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, eig_check_tol(h), s);
     HIPCHK(hipMemcpyAsync(M, h->tmpB, sizeof(cplx) * (size_t)m * q, hipMemcpyDeviceToDevice, s));
   } else {
     const int kg = k;
@@ -612,7 +620,7 @@ void truncate_bond(mps_sim* h, int i) {
     ZGemm gx = zgemm_args((int)m, q, kg, zop(M, k, 0), zop(h->tmpB, q, 0), h->tmpA, q, 0, one, zero);
     zgemm(gx, h->lw.gpart, h->lw.gpart_elems, s, &h->prof);
     norm2(h, h->tmpA, m * q, 3);
-    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, s);
+    launch_trunc_finalize(h->dscal, h->flog, h->dlogn, h->lw.lam, q, extra, h->lw.flag, eig_check_tol(h), s);
     // X = Q R': site i <- Q, C = R' V^H (q x k)
     qr_factor((int)m, q, h->tmpA, q, 1, h->lw, s);
     qr_form_q((int)m, q, h->tmpA, q, 1, h->lw, M, q, s);
@@ -788,7 +796,8 @@ void reset_bookkeeping(mps_sim* h) {
   HIPCHK(copy_sync(h, h->dscal, sc, sizeof(sc), hipMemcpyHostToDevice));
   int zero = 0;
   HIPCHK(copy_sync(h, h->lw.flag, &zero, sizeof(int), hipMemcpyHostToDevice));
-  HIPCHK(copy_sync(h, h->dlogn, &zero, sizeof(int), hipMemcpyHostToDevice));
+  int zeros[2] = {0, 0};
+  HIPCHK(copy_sync(h, h->dlogn, zeros, sizeof(zeros), hipMemcpyHostToDevice));
   h->nlog = 0;
   h->steps = 0;
 }
@@ -872,7 +881,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->env[1] = dalloc<cplx>(h, z.env);
     h->envx = dalloc<cplx>(h, z.envx);
     h->dscal = dalloc<double>(h, 16);
-    h->dlogn = dalloc<int>(h, 1);
+    h->dlogn = dalloc<int>(h, 2);
     h->dpartial = dalloc<double>(h, 4096);
     LinalgWork& w = h->lw;
     w.nmax = z.nmax; w.qmax = z.qmax; w.mmax = z.mmax;
@@ -911,6 +920,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
       w.Ab = dalloc<cplx>(h, l.band);
       w.Br = dalloc<cplx>(h, l.band);
       w.Ubuf = dalloc<cplx>(h, l.ubuf);
+      w.invit_batch = p.eig_batch;
       w.acc = dalloc<cplx>(h, l.acc);
     }
     // gate tables
@@ -966,6 +976,9 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     std::string m = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
     mps_free(h);
     return fail(nullptr, MPS_E_DEVICE, m);
+  } catch (BoundsError& e) {
+    mps_free(h);
+    return fail(nullptr, MPS_E_DEVICE, "operand out of bounds, not launched: " + e.msg);
   }
   *out = h;
   return MPS_OK;
@@ -983,6 +996,8 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
                                        hipGetErrorString(e.e));                              \
   } catch (NoMem&) {                                                                         \
     return fail((h), MPS_E_DEVICE, "device allocation failed");                              \
+  } catch (BoundsError & e) {                                                                \
+    return fail((h), MPS_E_DEVICE, "operand out of bounds, not launched: " + e.msg);         \
   }
 
 mps_status mps_apply_trotter_step(mps_handle h, int32_t nsteps) {
@@ -1035,15 +1050,18 @@ mps_status mps_measure(mps_handle h, double gamma, mps_obs* out) {
   if (!out) return fail(h, MPS_E_INVAL, "out is NULL");
   double e[3], ex[3] = {0.0, 0.0, 0.0};
   double sc[2];
+  int counts[2] = {0, 0};
   const bool xy = h->plan.model == 1;
   TRYDEV(h, measure_sweep(h, e, 0);
          if (xy) measure_sweep(h, ex, 1);
-         HIPCHK(copy_sync(h, sc, h->dscal, sizeof(sc), hipMemcpyDeviceToHost)));
+         HIPCHK(copy_sync(h, sc, h->dscal, sizeof(sc), hipMemcpyDeviceToHost));
+         HIPCHK(copy_sync(h, counts, h->dlogn, sizeof(counts), hipMemcpyDeviceToHost)));
   mps_status st = check_device(h);
   if (st != MPS_OK) return st;
   const double n = h->plan.n;
   mps_obs o{};
   o.step = h->steps;
+  o.eig_suspect = counts[1];
   o.norm = e[0];
   o.z = e[1] / (n * e[0]);
   o.z2 = xy ? ex[2] / (n * n * ex[0]) : e[2] / (n * n * e[0]);
@@ -1076,6 +1094,7 @@ void mps_free(mps_handle h) {
   (void)hipStreamSynchronize(h->stream);
   linalg_release(h->lw);
   for (void* p : h->allocations) {
+    bounds_unregister(p);
     if (h->has_alloc) h->alloc.free(h->alloc.ctx, p, (void*)h->stream);
     else (void)hipFree(p);
   }
@@ -1259,6 +1278,11 @@ mps_status mps_set_progress(mps_handle h, mps_progress_fn fn, void* ctx) {
   GUARD(h);
   h->progress = fn;
   h->progress_ctx = ctx;
+  return MPS_OK;
+}
+
+mps_status mps_debug_check_bounds(int32_t enable) {
+  bounds_set_checking(enable != 0);
   return MPS_OK;
 }
 

@@ -42,6 +42,7 @@ mps_status validate(const mps_config* cfg, const char** msg) {
   if (cfg->schedule < 1 || cfg->schedule > 4) { *msg = "schedule must be 1, 2, 3 or 4"; return MPS_E_INVAL; }
   if (cfg->periodic != 0 && cfg->periodic != 1) { *msg = "periodic must be 0 or 1"; return MPS_E_INVAL; }
   if (cfg->eig_path < 0 || cfg->eig_path > 2) { *msg = "eig_path must be 0, 1 or 2"; return MPS_E_INVAL; }
+  if (cfg->eig_batch < 0 || cfg->eig_batch > 1024) { *msg = "eig_batch must be in 0..1024"; return MPS_E_INVAL; }
   if (!std::isfinite(cfg->J) || !std::isfinite(cfg->h) || !std::isfinite(cfg->dt) ||
       !std::isfinite(cfg->theta0)) { *msg = "non-finite parameter"; return MPS_E_INVAL; }
   *msg = "";
@@ -302,6 +303,7 @@ void build_plan(const mps_config* cfg, Plan& p) {
   p.chi = cfg->chi_max; p.order = cfg->trotter_order; p.periodic = cfg->periodic;
   p.schedule = cfg->schedule;
   p.eig_path = cfg->eig_path;
+  p.eig_batch = cfg->eig_batch > 0 ? cfg->eig_batch : 1024;
   p.J = cfg->J; p.h = cfg->h; p.dt = cfg->dt; p.theta0 = cfg->theta0;
   p.model = cfg->model;
   if (cfg->model == 1) xy_geometry(cfg, p);

@@ -28,6 +28,7 @@ struct Plan {
   int nb = 0;                      // blocks
   std::vector<int> snake_order;    // block held by each site at the start
   int chi = 0, order = 1, periodic = 1, schedule = 1, eig_path = 0;
+  int eig_batch = 1024;            // vectors per band inverse-iteration launch
   double J = 0, h = 0, dt = 0, theta0 = 0;
   int wL = 0, wR = 0, dmax = 1;
   std::vector<int> block_width;               // per block id

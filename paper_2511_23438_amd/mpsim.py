@@ -44,17 +44,17 @@ class MpsConfig(C.Structure):
                 ("schedule", C.c_int32), ("periodic", C.c_int32), ("eig_path", C.c_int32),
                 ("J", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("theta0", C.c_double), ("seed", C.c_uint64), ("layers", C.c_int32),
-                ("model", C.c_int32)]
+                ("model", C.c_int32), ("eig_batch", C.c_int32)]
 
 
 class MpsObs(C.Structure):
-    _fields_ = [("step", C.c_int32), ("reserved", C.c_int32), ("z", C.c_double),
+    _fields_ = [("step", C.c_int32), ("eig_suspect", C.c_int32), ("z", C.c_double),
                 ("z2", C.c_double), ("norm", C.c_double), ("fidelity", C.c_double),
                 ("log_fidelity", C.c_double), ("z_rescaled", C.c_double),
                 ("z2_rescaled", C.c_double), ("gamma", C.c_double), ("min_gap", C.c_double)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for (k, _) in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for (k, _) in self._fields_}
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -101,6 +101,7 @@ _sig = {
     "mps_last_error": (C.c_char_p, [H]),
     "mps_measure_static": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
+    "mps_debug_check_bounds": (C.c_int, [C.c_int32]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -125,13 +126,16 @@ def _check(st: int, handle=None) -> None:
 def make_config(rows: int, cols: int, chi: int, J: float = -1.0, h: float = 2.0,
                 dt: float = 0.25, theta0: float = math.pi / 18, order: int = 1,
                 precision: str = "fp64", periodic: bool = True, seed: int = 0,
-                schedule: int = 1, eig_path: int = 0, layers: int = 0) -> MpsConfig:
+                schedule: int = 1, eig_path: int = 0, layers: int = 0,
+                eig_batch: int = 0) -> MpsConfig:
     """rows x cols grid with half-row blocks, or with layers >= 2 the
     rows x cols x layers cube with one qubit per site (schedule 3 or 4).
     schedule: 1 block pairs with routed wrap pairs, 2 rotating rows, 3 route
-    and return, 4 gate by gate (rank-2 operators and bond truncations)."""
+    and return, 4 gate by gate (rank-2 operators and bond truncations).
+    eig_batch: eigenvectors per band inverse-iteration launch (0: 1024)."""
     return MpsConfig(rows, cols, chi, PRECISION[precision], order, schedule,
-                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0)
+                     1 if periodic else 0, eig_path, J, h, dt, theta0, seed, layers, 0,
+                     eig_batch)
 
 
 def make_xy_config(rows: int, cols: int, chi: int, g: float = 1.0,
@@ -140,13 +144,14 @@ def make_xy_config(rows: int, cols: int, chi: int, g: float = 1.0,
     """XY-model quench (model 1): rows x cols grid, open boundaries, one qubit
     per site, coupling g, step dt, start state of preparation time tau."""
     return MpsConfig(rows, cols, chi, PRECISION[precision], 2, 3, 0, eig_path, g, 0.0, dt,
-                     tau, seed, 0, 1)
+                     tau, seed, 0, 1, 0)
 
 
 def config_from_instance(inst, seed: int = 0) -> MpsConfig:
     return make_config(inst.rows, inst.cols, inst.chi, inst.J, inst.h, inst.dt,
                        inst.theta0, inst.order, inst.precision, True, seed,
-                       getattr(inst, "schedule", 1), getattr(inst, "eig_path", 0))
+                       getattr(inst, "schedule", 1), getattr(inst, "eig_path", 0), 0,
+                       getattr(inst, "eig_batch", 0))
 
 
 def footprint_bytes(cfg: MpsConfig) -> int:
@@ -340,6 +345,12 @@ class Simulation:
         _check(_lib.mps_to_statevector(self.h, arr.ctypes.data_as(C.POINTER(C.c_double)), ln),
                self.h)
         return arr.view(np.complex128)
+
+
+def debug_check_bounds(enable: bool) -> None:
+    """mps_debug_check_bounds: host-side operand extent checks before the
+    library's GEMM, reflector, QR and eigensolver launches (process-wide)."""
+    _check(_lib.mps_debug_check_bounds(1 if enable else 0))
 
 
 def measure_static(bonds: Sequence[int], dims: Sequence[int], site_ptrs: Sequence[int],

@@ -29,6 +29,7 @@ class Instance:
     order: int = 1
     precision: str = "fp64"          # fp64 | c64 | bf16x3
     schedule: int = 1                # 1: routed wrap pairs, 2: rotating rows
+    eig_batch: int = 0               # eigenvectors per band inverse-iteration launch (0: 1024)
     name: str = ""
 
     def as_dict(self):

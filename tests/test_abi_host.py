@@ -94,6 +94,20 @@ def test_footprint_monotone_and_fits():
     assert fp[2] < 288 * 2 ** 30
 
 
+def test_eig_batch_bounds_the_inverse_iteration_workspace():
+    """6x8, chi = 1024 (Gram side 16384, two-stage): 256 vectors per band
+    inverse-iteration launch instead of 1024 saves the LU rows (99 complex
+    per Gram row) of 768 vectors; out-of-range values are rejected."""
+    fp = {b: mpsim.footprint_bytes(mpsim.make_config(6, 8, 1024, schedule=2, eig_batch=b))
+          for b in (0, 1024, 256)}
+    assert fp[0] == fp[1024]
+    assert fp[1024] - fp[256] == 768 * 16384 * 99 * 16
+    for bad in (-1, 1025):
+        with pytest.raises(mpsim.MpsError) as e:
+            mpsim.footprint_bytes(mpsim.make_config(6, 8, 1024, eig_batch=bad))
+        assert e.value.status == mpsim.MPS_E_INVAL
+
+
 @pytest.mark.parametrize("shape", [(2, 3), (3, 3), (4, 4), (1, 5), (6, 6), (5, 4)])
 def test_xy_schedule_equals_oracle(shape):
     """XY model: the C++ planner's sublayer / route-and-return list equals the

@@ -74,6 +74,7 @@ def test_bulk_update_matches_oracle(path):
         e1 = np.max(np.abs(sv[big] - gsv[big]))
         say("kept singular values: squared error %.2e, error above 1e-3 %.2e" % (e2, e1))
         assert e2 < 1e-12 and e1 < 1e-10
+        assert sim.measure()["eig_suspect"] == 0
     finally:
         sim.free()
 
@@ -127,5 +128,6 @@ def test_bulk_update_reduced_precision(path, prec):
         say("%s %s: f rel err %.2e, block entries rel err %.2e, singular values rel err %.2e"
             % (os.path.basename(path), prec, ef, et, es))
         assert ef < 1e-5 and et < 1e-5 and es < 1e-5
+        assert sim.measure()["eig_suspect"] == 0
     finally:
         sim.free()

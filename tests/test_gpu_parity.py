@@ -253,6 +253,8 @@ def test_config_4x4_chi16_every_update_replayed(seed):
     first = int(np.argmax(g1 < 1e-8)) if np.any(g1 < 1e-8) else len(g1)
     assert np.max(np.abs(f1[:first] - f2[:first])) < 1e-12
     assert sim2.bond_dims() == sim.bond_dims() and sim2.site_blocks() == sim.site_blocks()
+    # every truncation's kept weight equals the sum of its kept eigenvalues
+    assert sim.measure()["eig_suspect"] == 0 and sim2.measure()["eig_suspect"] == 0
 
 
 def test_config_5x6_c64_every_update_replayed():
@@ -350,6 +352,7 @@ def test_random_state_truncating_parity(R, C, chi, init_chi, steps, seed, order)
     f_ora = np.array([u["f"] for u in ora.update_log])
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
     assert sim.bond_dims() == ora.bond_dims()
+    assert sim.measure()["eig_suspect"] == 0
 
 
 @pytest.mark.parametrize("prec", ["c64", "bf16x3"])
@@ -371,6 +374,7 @@ def test_reduced_precision_against_fp64_oracle(prec, R, C, chi, steps, seed):
         print(prec, R, C, chi, "step", s_ + 1, "err z %.2e z2 %.2e F(rel) %.2e" % (ez, ez2, ef))
         assert ez < 1e-5 and ez2 < 1e-5 and ef < 1e-5
         assert abs(a["norm"] - 1) < 1e-5    # measured with reduced-precision contractions
+        assert a["eig_suspect"] == 0
 
 
 @pytest.mark.parametrize("R,C,chi,steps,order", [(4, 4, 256, 2, 1), (3, 4, 64, 3, 1),
@@ -465,6 +469,34 @@ def test_two_stage_truncating_parity(R, C, chi, steps, seed):
     f_gpu, _ = sim.truncation_log()
     f_ora = np.array([u["f"] for u in ora.update_log])
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
+
+
+def test_band_invit_batching_changes_nothing():
+    """The band inverse iteration run 7 vectors per launch (q = 64: ten
+    launches, the last one with a single vector) gives the same bits as one
+    launch for all vectors, and the oracle's truncation."""
+    R, C, chi, seed = 5, 6, 64, 42
+    sites, centre = workloads.random_mps(R, C, chi, seed)
+    runs = []
+    for batch in (0, 7):
+        sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, eig_path=2,
+                                                 eig_batch=batch))
+        sim.set_state(sites, centre)
+        sim.step(1)
+        runs.append((sim.truncation_log()[0], sim.measure(),
+                     [sim.get_site(p) for p in range(2 * R)]))
+        sim.free()
+    (fa, oa, sa), (fb, ob, sb) = runs
+    assert np.array_equal(fa, fb)
+    for k in ("z", "z2", "log_fidelity"):
+        assert oa[k] == ob[k]
+    for x, y in zip(sa, sb):
+        assert np.array_equal(x, y)
+    assert oa["eig_suspect"] == 0
+    ora = omps.BlockMPS.from_sites(Grid(R, C), chi, sites, centre, J, H, DT)
+    ora.step()
+    f_ora = np.array([u["f"] for u in ora.update_log])
+    assert np.max(np.abs(fb - f_ora)) < TOL
 
 
 def test_one_and_two_stage_agree_on_wide_gram():
