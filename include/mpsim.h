@@ -289,6 +289,20 @@ mps_status mps_profile_min_work(mps_handle h, double min_work);
  * algorithmic work (bytes or flops, per the class). Synchronises. */
 mps_status mps_profile_read(mps_handle h, double* total_ms, int64_t* launches, double* work);
 
+/* The truncation's eigensolver on its own (results section: the kept
+ * subspace of a bond is the top-q eigenspace of the Gram matrix of the
+ * two-site block), for tests of the solver on chosen spectra. gram: host,
+ * n x n Hermitian complex128, column-major (only the lower triangle is
+ * read). eig_path: 1 one-stage (Householder tridiagonalisation), 2
+ * two-stage (dense -> band -> tridiagonal); seed: start vectors of the
+ * inverse iteration. Outputs (host): lam[0..q-1] the q largest eigenvalues,
+ * descending; vecs the n x q row-major complex128 eigenvectors (column j
+ * for lam[j], orthonormal columns). 1 <= q <= n. Allocates and frees its
+ * own device workspace; synchronous on hip_stream (NULL: the default
+ * stream). MPS_E_INVAL for bad arguments, MPS_E_NOMEM, MPS_E_DEVICE. */
+mps_status mps_eigh_top(int32_t n, int32_t q, int32_t eig_path, uint64_t seed, const double* gram,
+                        double* lam, double* vecs, void* hip_stream);
+
 /* Operand extent checks (diagnostic, process-wide, off by default). While
  * enabled (enable != 0), every complex GEMM, reflector extraction, QR and
  * eigensolver launch is preceded by a host-side check that each operand's

@@ -10,16 +10,24 @@ namespace mpsim {
 
 constexpr int TRD_NB = 32, QR_NB = 32, BT_NB = 64;
 
+// Columns whose norm is below sqrt(DBL_MIN / DBL_EPSILON) ~ 1e-146 are taken
+// as zero: the squares of their entries can underflow, so |x|^2 (a sum of
+// squares) would understate the column and the reflector built from it
+// would not be unitary (and a norm of 0 with alpha != 0 would divide by
+// zero). Every matrix reduced here has a norm of order one or larger.
+constexpr double REFLECTOR_FLOOR = 1.0010415475915505e-146;
+
 // Reflector H = I - tau v v^H with v = [1; x*scale] such that
-// H^H [alpha; x] = [beta; 0], beta real.
+// H^H [alpha; x] = [beta; 0], beta real. A column below REFLECTOR_FLOOR is
+// left as it is (tau = 0, beta = Re alpha).
 __device__ inline void reflector(cplx alpha, double xnorm2, double& beta, cplx& tau, cplx& scale) {
-  if (xnorm2 == 0.0 && alpha.y == 0.0) {
+  const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+  if ((xnorm2 == 0.0 && alpha.y == 0.0) || nrm < REFLECTOR_FLOOR) {
     beta = alpha.x;
     tau = make_double2(0.0, 0.0);
     scale = make_double2(0.0, 0.0);
     return;
   }
-  double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
   beta = (alpha.x >= 0.0) ? -nrm : nrm;
   tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
   scale = cinv(make_double2(alpha.x - beta, alpha.y));

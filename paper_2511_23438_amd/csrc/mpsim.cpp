@@ -211,6 +211,50 @@ LwSizes lw_sizes(const Sizes& z) {
   return l;
 }
 
+// The eigensolver, QR and reflector workspaces of one handle.
+void alloc_linalg(mps_sim* h, const Sizes& z, const LwSizes& l) {
+  LinalgWork& w = h->lw;
+  w.nmax = z.nmax; w.qmax = z.qmax; w.mmax = z.mmax;
+  w.W = dalloc<cplx>(h, l.W);
+  w.tpart = dalloc<cplx>(h, l.tpart);
+  w.tpart_elems = l.tpart;
+  w.P = dalloc<cplx>(h, l.P);
+  w.P_elems = l.P;
+  w.dpart = dalloc<cplx>(h, l.dpart);
+  w.tsum = dalloc<cplx>(h, 2 * TRD_NB + 2);
+  w.npart = dalloc<double>(h, l.npart);
+  w.d = dalloc<double>(h, z.nmax);
+  w.e = dalloc<double>(h, z.nmax);
+  w.e2 = dalloc<double>(h, z.nmax);
+  w.tau = dalloc<cplx>(h, z.nmax);
+  w.qtau = dalloc<cplx>(h, z.colmax);
+  w.scal = dalloc<double>(h, 16);
+  w.lam = dalloc<double>(h, z.qmax + 2);
+  w.iwork = dalloc<double>(h, l.iwork);
+  w.T = dalloc<cplx>(h, l.T);
+  w.T_elems = l.T;
+  w.S = dalloc<cplx>(h, 4096);
+  w.wmax = z.colmax;
+  w.W1 = dalloc<cplx>(h, l.W12);
+  w.W2 = dalloc<cplx>(h, l.W12);
+  w.vmax = std::max(z.nmax, z.mmax);
+  w.V = dalloc<cplx>(h, l.V);
+  w.gpart = dalloc<cplx>(h, l.gpart);
+  w.gpart_elems = l.gpart;
+  w.flag = dalloc<int>(h, 4);
+  w.prof = &h->prof;
+  if (l.T1) {
+    w.T1 = dalloc<cplx>(h, l.T1);
+    w.X2 = dalloc<cplx>(h, l.X2);
+    w.S2 = dalloc<cplx>(h, 4096);
+    w.Ab = dalloc<cplx>(h, l.band);
+    w.Br = dalloc<cplx>(h, l.band);
+    w.Ubuf = dalloc<cplx>(h, l.ubuf);
+    w.invit_batch = z.eig_batch;
+    w.acc = dalloc<cplx>(h, l.acc);
+  }
+}
+
 size_t footprint(const Plan& p) {
   Sizes z = plan_sizes(p);
   LwSizes l = lw_sizes(z);
@@ -883,46 +927,7 @@ mps_status mps_init_product(const mps_config* cfg, const mps_allocator* alloc, v
     h->dscal = dalloc<double>(h, 16);
     h->dlogn = dalloc<int>(h, 2);
     h->dpartial = dalloc<double>(h, 4096);
-    LinalgWork& w = h->lw;
-    w.nmax = z.nmax; w.qmax = z.qmax; w.mmax = z.mmax;
-    w.W = dalloc<cplx>(h, l.W);
-    w.tpart = dalloc<cplx>(h, l.tpart);
-    w.tpart_elems = l.tpart;
-    w.P = dalloc<cplx>(h, l.P);
-    w.P_elems = l.P;
-    w.dpart = dalloc<cplx>(h, l.dpart);
-    w.tsum = dalloc<cplx>(h, 2 * TRD_NB + 2);
-    w.npart = dalloc<double>(h, l.npart);
-    w.d = dalloc<double>(h, z.nmax);
-    w.e = dalloc<double>(h, z.nmax);
-    w.e2 = dalloc<double>(h, z.nmax);
-    w.tau = dalloc<cplx>(h, z.nmax);
-    w.qtau = dalloc<cplx>(h, z.colmax);
-    w.scal = dalloc<double>(h, 16);
-    w.lam = dalloc<double>(h, z.qmax + 2);
-    w.iwork = dalloc<double>(h, l.iwork);
-    w.T = dalloc<cplx>(h, l.T);
-    w.T_elems = l.T;
-    w.S = dalloc<cplx>(h, 4096);
-    w.wmax = z.colmax;
-    w.W1 = dalloc<cplx>(h, l.W12);
-    w.W2 = dalloc<cplx>(h, l.W12);
-    w.vmax = std::max(z.nmax, z.mmax);
-    w.V = dalloc<cplx>(h, l.V);
-    w.gpart = dalloc<cplx>(h, l.gpart);
-    w.gpart_elems = l.gpart;
-    w.flag = dalloc<int>(h, 4);
-    w.prof = &h->prof;
-    if (l.T1) {
-      w.T1 = dalloc<cplx>(h, l.T1);
-      w.X2 = dalloc<cplx>(h, l.X2);
-      w.S2 = dalloc<cplx>(h, 4096);
-      w.Ab = dalloc<cplx>(h, l.band);
-      w.Br = dalloc<cplx>(h, l.band);
-      w.Ubuf = dalloc<cplx>(h, l.ubuf);
-      w.invit_batch = p.eig_batch;
-      w.acc = dalloc<cplx>(h, l.acc);
-    }
+    alloc_linalg(h, z, l);
     // gate tables
     long off = 0;
     for (auto& t : p.pair_phase) { h->pair_off.push_back(off); off += (long)t.size(); }
@@ -1278,6 +1283,52 @@ mps_status mps_set_progress(mps_handle h, mps_progress_fn fn, void* ctx) {
   GUARD(h);
   h->progress = fn;
   h->progress_ctx = ctx;
+  return MPS_OK;
+}
+
+mps_status mps_eigh_top(int32_t n, int32_t q, int32_t eig_path, uint64_t seed, const double* gram,
+                        double* lam, double* vecs, void* hip_stream) {
+  if (n < 1 || q < 1 || q > n || (eig_path != 1 && eig_path != 2) || !gram || !lam || !vecs)
+    return fail(nullptr, MPS_E_INVAL, "mps_eigh_top: bad arguments");
+  mps_sim* h = new mps_sim();
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  mps_status st = MPS_OK;
+  std::string msg;
+  try {
+    Sizes z;
+    z.nmax = n; z.qmax = q; z.mmax = n;
+    z.colmax = std::max<long>(q, TRD_NB);
+    z.eig_path = eig_path;
+    const LwSizes l = lw_sizes(z);
+    alloc_linalg(h, z, l);
+    h->gram = dalloc<cplx>(h, (long)n * n);
+    h->tmpA = dalloc<cplx>(h, (long)n * q);
+    h->tmpB = dalloc<cplx>(h, (long)n * q);
+    HIPCHK(hipMemsetAsync(h->lw.flag, 0, 4 * sizeof(int), h->stream));
+    HIPCHK(hipMemcpyAsync(h->gram, gram, sizeof(cplx) * (size_t)n * n, hipMemcpyHostToDevice, h->stream));
+    if (eig_path == 2) heev_top_2stage(n, h->gram, n, q, h->tmpB, q, h->tmpA, h->lw, seed, h->stream);
+    else heev_top(n, h->gram, n, q, h->tmpB, q, h->tmpA, h->lw, seed, h->stream);
+    HIPCHK(hipGetLastError());
+    const int extra = (q < n) ? 1 : 0;
+    std::vector<double> asc(q + extra);
+    HIPCHK(hipMemcpyAsync(asc.data(), h->lw.lam, sizeof(double) * asc.size(), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipMemcpyAsync(vecs, h->tmpB, sizeof(cplx) * (size_t)n * q, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int j = 0; j < q; ++j) lam[j] = asc[extra + q - 1 - j];
+  } catch (NoMem&) {
+    st = MPS_E_NOMEM;
+    msg = "mps_eigh_top: device allocation failed";
+  } catch (HipError& e) {
+    st = MPS_E_DEVICE;
+    msg = std::string("mps_eigh_top: HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+  } catch (BoundsError& e) {
+    st = MPS_E_DEVICE;
+    msg = "mps_eigh_top: operand out of bounds, not launched: " + e.msg;
+  }
+  mps_free(h);
+  if (st != MPS_OK) return fail(nullptr, st, msg);
   return MPS_OK;
 }
 

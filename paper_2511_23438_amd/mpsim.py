@@ -102,6 +102,9 @@ _sig = {
     "mps_measure_static": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "mps_debug_check_bounds": (C.c_int, [C.c_int32]),
+    "mps_eigh_top": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.c_void_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -345,6 +348,21 @@ class Simulation:
         _check(_lib.mps_to_statevector(self.h, arr.ctypes.data_as(C.POINTER(C.c_double)), ln),
                self.h)
         return arr.view(np.complex128)
+
+
+def eigh_top(G: np.ndarray, q: int, eig_path: int = 1, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """mps_eigh_top: the q largest eigenvalues (descending) of the Hermitian
+    n x n matrix G and their eigenvectors (n x q), by the library's
+    truncation eigensolver (eig_path 1 one-stage, 2 two-stage)."""
+    n = int(G.shape[0])
+    g = np.asfortranarray(np.asarray(G, dtype=np.complex128)).reshape(-1, order="F").view(np.float64)
+    g = np.ascontiguousarray(g)
+    lam = np.zeros(q, dtype=np.float64)
+    vecs = np.zeros((n, q), dtype=np.complex128)
+    dp = C.POINTER(C.c_double)
+    _check(_lib.mps_eigh_top(n, int(q), int(eig_path), int(seed), g.ctypes.data_as(dp),
+                             lam.ctypes.data_as(dp), vecs.view(np.float64).ctypes.data_as(dp), None))
+    return lam, vecs
 
 
 def debug_check_bounds(enable: bool) -> None:

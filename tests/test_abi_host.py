@@ -135,3 +135,13 @@ def test_xy_invalid_configs(field, value):
 def test_xy_footprint():
     fp = mpsim.footprint_bytes(mpsim.make_xy_config(6, 6, 256))
     assert 0 < fp < 8 * 2 ** 30
+
+
+def test_eigh_top_rejects_bad_arguments():
+    """mps_eigh_top validates its arguments on the host before any device
+    work: q outside 1..n or an unknown eigensolver path."""
+    G = np.eye(4, dtype=np.complex128)
+    for q, path in ((0, 1), (5, 1), (2, 3)):
+        with pytest.raises(mpsim.MpsError) as e:
+            mpsim.eigh_top(G, q, eig_path=path)
+        assert e.value.status == mpsim.MPS_E_INVAL

@@ -96,6 +96,30 @@ def test_full_bond_dimension_matches_state_vector(R, C, chi, steps, order):
     assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < TOL
 
 
+@pytest.mark.parametrize("schedule,eig_path", [(1, 1), (1, 2), (2, 1), (4, 1), (4, 2)])
+@pytest.mark.parametrize("R,C,chi", [(3, 4, 64), (4, 4, 256)])
+def test_all_zero_start_full_bond_dimension_matches_state_vector(R, C, chi, schedule, eig_path):
+    """theta0 = 0 (every qubit in |0>): the first updates act on product
+    states, so most kept singular values are exact zeros and the rest of
+    the Gram matrices are rounding residues many orders below the leading
+    entries (columns whose squares underflow must be taken as zero by the
+    reflectors). At full bond dimension the exact Trotter state, in every
+    schedule and with both eigensolvers."""
+    g = Grid(R, C)
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, schedule=schedule,
+                                             eig_path=eig_path))
+    sv = osv.StateVector(g, 0.0, J, H, DT, 1)
+    for _ in range(2):
+        sim.step(1)
+        sv.step()
+        a, b = sim.measure(), sv.measure()
+        assert abs(a["z"] - b["z"]) < TOL and abs(a["z2"] - b["z2"]) < TOL
+        assert abs(a["log_fidelity"]) < 1e-12 and a["eig_suspect"] == 0
+    psi = sim.to_statevector()
+    assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < TOL
+    sim.free()
+
+
 def test_no_coupling_precession_closed_form():
     th = 0.41
     sim = mpsim.Simulation(mpsim.make_config(3, 4, 4, J=0.0, theta0=th))
@@ -167,7 +191,7 @@ def _oracle_from_gpu(sim, R, C, chi, order=1, schedule=1):
     return m
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, None])
+@pytest.mark.parametrize("seed", [0, 1, 2, None, "zero"])
 def test_config_4x4_chi16_every_update_replayed(seed):
     """The 4x4, d = 4, chi = 16 workload, 20 steps from the product state,
     driven op by op through the C-ABI. Before every two-site update the GPU's
@@ -182,8 +206,12 @@ def test_config_4x4_chi16_every_update_replayed(seed):
     degenerate multiplets (the lattice symmetries of the product state make
     many)."""
     from oracle import estimators
-    inst = workloads.small_4x4(seed) if seed is not None else workloads.Instance(
-        4, 4, 16, theta0=math.pi / 18)
+    if seed == "zero":                      # the end of the theta0 range: every qubit in |0>
+        inst = workloads.Instance(4, 4, 16, theta0=0.0)
+    elif seed is None:
+        inst = workloads.Instance(4, 4, 16, theta0=math.pi / 18)
+    else:
+        inst = workloads.small_4x4(seed)
     R, C, chi, steps, gamma = 4, 4, 16, 20, 0.647
     cfg = mpsim.make_config(R, C, chi, theta0=inst.theta0)
     sim = mpsim.Simulation(cfg)
@@ -251,7 +279,8 @@ def test_config_4x4_chi16_every_update_replayed(seed):
     f2, _ = sim2.truncation_log()
     assert len(f2) == len(f1)
     first = int(np.argmax(g1 < 1e-8)) if np.any(g1 < 1e-8) else len(g1)
-    assert np.max(np.abs(f1[:first] - f2[:first])) < 1e-12
+    if first > 0:
+        assert np.max(np.abs(f1[:first] - f2[:first])) < 1e-12
     assert sim2.bond_dims() == sim.bond_dims() and sim2.site_blocks() == sim.site_blocks()
     # every truncation's kept weight equals the sum of its kept eigenvalues
     assert sim.measure()["eig_suspect"] == 0 and sim2.measure()["eig_suspect"] == 0
