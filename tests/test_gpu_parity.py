@@ -96,19 +96,20 @@ def test_full_bond_dimension_matches_state_vector(R, C, chi, steps, order):
     assert abs(abs(np.vdot(sv.psi, psi)) ** 2 - 1) < TOL
 
 
-@pytest.mark.parametrize("schedule,eig_path", [(1, 1), (1, 2), (2, 1), (4, 1), (4, 2)])
+@pytest.mark.parametrize("schedule,eig_path,th", [(1, 1, 0.0), (1, 2, 0.0), (2, 1, 0.0), (4, 1, 0.0),
+                                                  (4, 2, 0.0), (1, 1, math.pi / 2), (2, 2, math.pi)])
 @pytest.mark.parametrize("R,C,chi", [(3, 4, 64), (4, 4, 256)])
-def test_all_zero_start_full_bond_dimension_matches_state_vector(R, C, chi, schedule, eig_path):
-    """theta0 = 0 (every qubit in |0>): the first updates act on product
-    states, so most kept singular values are exact zeros and the rest of
-    the Gram matrices are rounding residues many orders below the leading
-    entries (columns whose squares underflow must be taken as zero by the
-    reflectors). At full bond dimension the exact Trotter state, in every
-    schedule and with both eigensolvers."""
+def test_all_zero_start_full_bond_dimension_matches_state_vector(R, C, chi, schedule, eig_path, th):
+    """theta0 = 0 (every qubit in |0>), pi/2 and pi: the first updates act on
+    product states, so most kept singular values are exact zeros and the
+    rest of the Gram matrices are rounding residues many orders below the
+    leading entries (columns whose squares underflow must be taken as zero
+    by the reflectors). At full bond dimension the exact Trotter state, in
+    every schedule and with both eigensolvers."""
     g = Grid(R, C)
-    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=0.0, schedule=schedule,
+    sim = mpsim.Simulation(mpsim.make_config(R, C, chi, theta0=th, schedule=schedule,
                                              eig_path=eig_path))
-    sv = osv.StateVector(g, 0.0, J, H, DT, 1)
+    sv = osv.StateVector(g, th, J, H, DT, 1)
     for _ in range(2):
         sim.step(1)
         sv.step()
@@ -547,16 +548,18 @@ def test_one_and_two_stage_agree_on_wide_gram():
     assert abs(o1["z"] - o2["z"]) < TOL and abs(o1["z2"] - o2["z2"]) < TOL
 
 
-@pytest.mark.parametrize("shape,chi,steps,order", [((2, 2, 3), 64, 2, 1), ((2, 2, 2), 16, 3, 2),
-                                                    ((1, 3, 4), 64, 2, 1)])
-def test_cube_full_bond_dimension_matches_state_vector(shape, chi, steps, order):
-    """Cube with one qubit per site (open boundaries), route-and-return
-    schedule: at full bond dimension the HIP path is the exact Trotter state."""
+@pytest.mark.parametrize("shape,chi,steps,order,th,sched", [
+    ((2, 2, 3), 64, 2, 1, 0.6, 3), ((2, 2, 2), 16, 3, 2, 0.6, 3), ((1, 3, 4), 64, 2, 1, 0.6, 3),
+    ((2, 2, 3), 64, 2, 1, 0.0, 3), ((2, 2, 3), 64, 2, 1, 0.0, 4), ((2, 2, 2), 16, 2, 2, math.pi, 3)])
+def test_cube_full_bond_dimension_matches_state_vector(shape, chi, steps, order, th, sched):
+    """Cube with one qubit per site (open boundaries), route-and-return and
+    gate-by-gate schedules: at full bond dimension the HIP path is the exact
+    Trotter state, also from the all-|0> and all-|1> product states (exact
+    zeros kept at every truncation)."""
     from oracle.lattice import Cube
     lx, ly, lz = shape
     g = Cube(lx, ly, lz)
-    th = 0.6
-    sim = mpsim.Simulation(mpsim.make_config(lx, ly, chi, theta0=th, order=order, schedule=3,
+    sim = mpsim.Simulation(mpsim.make_config(lx, ly, chi, theta0=th, order=order, schedule=sched,
                                              layers=lz, periodic=False))
     sv = osv.StateVector(g, th, J, H, DT, order)
     for _ in range(steps):
