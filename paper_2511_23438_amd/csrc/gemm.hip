@@ -188,9 +188,23 @@ __device__ inline void store_b(double (*Bs)[BK][BN], const cplx r[4], int conj) 
   }
 }
 
+// The C value that an element's store epilogue adds (beta*C), read before
+// any of the workgroup's stores: as far as the compiler knows C may alias
+// the stored elements, so loads placed between the stores would each wait
+// for their data in turn. Zero where the epilogue reads no C.
+__device__ inline cplx load_c(const ZGemmDev& gd, int bat, long row, long col) {
+  const ZGemm& g = gd.g;
+  if (gd.ksplit > 1 || g.epi != EPI_STORE || (g.beta.x == 0.0 && g.beta.y == 0.0) || row >= g.M ||
+      col >= g.N)
+    return make_double2(0.0, 0.0);
+  const cplx* C = g.C + (long)bat * g.strideC;
+  return C[g.transC ? col * g.ldc + row : row * g.ldc + col];
+}
+
 // Store one result element: split-K partial, theta epilogue (phase, SWAP
-// layout) or alpha*val + beta*C.
-__device__ inline void store_out(const ZGemmDev& gd, int bz, int bat, long row, long col, cplx val) {
+// layout) or alpha*val + beta*C, with C read beforehand by load_c.
+__device__ inline void store_out(const ZGemmDev& gd, int bz, int bat, long row, long col, cplx val,
+                                 cplx cprev) {
   const ZGemm& g = gd.g;
   if (row >= g.M || col >= g.N) return;
   if (gd.ksplit > 1) {
@@ -211,7 +225,7 @@ __device__ inline void store_out(const ZGemmDev& gd, int bz, int bat, long row, 
   }
   const long idx = g.transC ? col * g.ldc + row : row * g.ldc + col;
   cplx out = cmul(g.alpha, val);
-  if (g.beta.x != 0.0 || g.beta.y != 0.0) out = cadd(out, cmul(g.beta, C[idx]));
+  if (g.beta.x != 0.0 || g.beta.y != 0.0) out = cadd(out, cmul(g.beta, cprev));
   C[idx] = out;
 }
 
@@ -291,6 +305,14 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemmDev gd) {
   }
 
   // epilogue (f64 result layout: register v of lane l is row 4v + l/16)
+  cplx cp[NA][2][4];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cp[a][b][v] = load_c(gd, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + wc + b * 16 + (l & 15));
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -299,7 +321,8 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemmDev gd) {
       for (int v = 0; v < 4; ++v)
         store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + wc + b * 16 + (l & 15),
                   make_double2(t1[a][b][v] - t2[a][b][v],
-                               t3[a][b][v] - t1[a][b][v] - t2[a][b][v]));
+                               t3[a][b][v] - t1[a][b][v] - t2[a][b][v]),
+                  cp[a][b][v]);
 }
 
 
@@ -408,6 +431,14 @@ __global__ __launch_bounds__(256) void cgemm_f32_kernel(ZGemmDev gd) {
         }
     }
   }
+  cplx cp[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cp[a][b][v] = load_c(gd, bat, m0 + wr + a * 16 + 4 * (l >> 4) + v, n0 + wc + b * 16 + (l & 15));
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -415,7 +446,7 @@ __global__ __launch_bounds__(256) void cgemm_f32_kernel(ZGemmDev gd) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * (l >> 4) + v, n0 + wc + b * 16 + (l & 15),
-                  make_double2((double)cr[a][b][v], (double)ci[a][b][v]));
+                  make_double2((double)cr[a][b][v], (double)ci[a][b][v]), cp[a][b][v]);
 }
 
 // Three-term bf16 split: x = hi + mid + lo with hi = bf16(x),
@@ -566,6 +597,14 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
       }
     }
   }
+  cplx cp[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cp[a][b][v] = load_c(gd, bat, m0 + wr + a * 16 + 4 * (l >> 4) + v, n0 + wc + b * 16 + (l & 15));
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -573,7 +612,7 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(ZGemmDev gd) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * (l >> 4) + v, n0 + wc + b * 16 + (l & 15),
-                  make_double2((double)cr[a][b][v], (double)ci[a][b][v]));
+                  make_double2((double)cr[a][b][v], (double)ci[a][b][v]), cp[a][b][v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -721,6 +760,14 @@ __global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
         }
     }
   }
+  cplx cp[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cp[a][b][v] = load_c(gd, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + b * 16 + (l & 15));
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -729,7 +776,8 @@ __global__ __launch_bounds__(256, 2) void zhemm_n32_kernel(ZGemmDev gd) {
       for (int v = 0; v < 4; ++v)
         store_out(gd, bz, bat, m0 + wr + a * 16 + 4 * v + (l >> 4), n0 + b * 16 + (l & 15),
                   make_double2(t1[a][b][v] - t2[a][b][v],
-                               t3[a][b][v] - t1[a][b][v] - t2[a][b][v]));
+                               t3[a][b][v] - t1[a][b][v] - t2[a][b][v]),
+                  cp[a][b][v]);
 }
 
 // Sum the split-K partials and apply the store epilogue.
@@ -740,6 +788,10 @@ __global__ void zgemm_reduce(ZGemmDev gd) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
     long row = e / g.N, col = e % g.N;
+    cplx* C = g.C + (long)bat * g.strideC;
+    const long idx = g.transC ? col * g.ldc + row : row * g.ldc + col;
+    const bool addc = g.beta.x != 0.0 || g.beta.y != 0.0;
+    const cplx cprev = addc ? C[idx] : make_double2(0.0, 0.0);
     cplx s = make_double2(0, 0);
     // 16 loads in flight per round; summation order k = 0, 1, ... as a plain loop
     for (int k0 = 0; k0 < gd.ksplit; k0 += 16) {
@@ -751,10 +803,8 @@ __global__ void zgemm_reduce(ZGemmDev gd) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) s = cadd(s, pv[i]);
     }
-    cplx* C = g.C + (long)bat * g.strideC;
-    const long idx = g.transC ? col * g.ldc + row : row * g.ldc + col;
     cplx out = cmul(g.alpha, s);
-    if (g.beta.x != 0.0 || g.beta.y != 0.0) out = cadd(out, cmul(g.beta, C[idx]));
+    if (addc) out = cadd(out, cmul(g.beta, cprev));
     C[idx] = out;
   }
 }
