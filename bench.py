@@ -437,6 +437,62 @@ def state_rate(sites, centre, rows: int, cols: int, chi: int, precision: str, sc
         sim.free()
 
 
+def step_model_flops(rows: int, cols: int, chi: int, schedule: int, order: int = 1):
+    """Algorithmic work of one step at saturated bonds, in flops of the
+    standard two-site update (8 flops per complex multiply-add): per update
+    the theta contraction 8 m n b1, the Gram matrix on the smaller side
+    (lower half) 4 kg (kg + 1) o, the reduction of that Hermitian matrix
+    (16/3) kg^3, the back-transformation of the q kept vectors 8 kg^2 q and
+    C = U^H theta 8 q kg o (m x n the theta shape, kg x o its sides after a
+    SWAP, q = min(chi, kg)); plus the measurement sweep (three environments,
+    two products per site). The factored Gram matrix of updates without
+    SWAP does less than this. None for the gate-by-gate schedule."""
+    if schedule not in (1, 2, 3):
+        return None
+    from paper_2511_23438_amd import mpsim
+    cfg = mpsim.make_config(rows, cols, chi, schedule=schedule, order=order)
+    ops = mpsim.schedule_dump(cfg, 1)
+    wl, wr = (cols + 1) // 2, cols // 2
+    n_sites = 2 * rows
+
+    def dim(b: int) -> int:
+        return 2 ** (wl if b % 2 == 0 else wr)
+
+    pos = []
+    for r in range(rows):
+        pos += [2 * r, 2 * r + 1] if r % 2 == 0 else [2 * r + 1, 2 * r]
+
+    def caps() -> list:
+        dims = [dim(b) for b in pos]
+        out = []
+        for p in range(n_sites + 1):
+            left = math.prod(dims[:p])
+            right = math.prod(dims[p:])
+            out.append(min(chi, left, right))
+        return out
+
+    total = 0.0
+    for kind, site, swap, _gate, _ba, _bb in ops.tolist():
+        if kind != 1:
+            continue
+        c = caps()
+        b0, b1, b2 = c[site], c[site + 1], c[site + 2]
+        d1, d2 = dim(pos[site]), dim(pos[site + 1])
+        m, n = b0 * d1, d2 * b2
+        mo, no = (b0 * d2, d1 * b2) if swap else (m, n)
+        kg, o = min(mo, no), max(mo, no)
+        q = min(chi, kg)
+        total += (8.0 * m * n * b1 + 4.0 * kg * (kg + 1) * o + 16.0 / 3.0 * kg ** 3
+                  + 8.0 * kg * kg * q + 8.0 * q * kg * o)
+        if swap:
+            pos[site], pos[site + 1] = pos[site + 1], pos[site]
+    c = caps()
+    for p in range(n_sites):
+        b, d, b2 = c[p], dim(pos[p]), c[p + 1]
+        total += 3 * (8.0 * b * b * d * b2 + 8.0 * b2 * b2 * b * d)
+    return total
+
+
 def roofline(prof: dict, elapsed: float) -> dict:
     bound = DOMINANT[prof["kernel"]]
     peak, unit = PEAK[bound]
@@ -612,6 +668,17 @@ def main() -> int:
     workload = "tfim_%dx%d_chi%d" % (args.rows, args.cols, args.chi)
     roof = roofline(head["prof"], head["seconds"])
     roof["traffic"] = read_traffic(args.prof, workload)
+    # the whole step against the float64 matrix peak (the standard method's
+    # algorithmic flops at saturated bonds; the contractions of the reduced
+    # modes are counted at that peak too)
+    try:
+        model = step_model_flops(args.rows, args.cols, args.chi, args.schedule)
+    except Exception as e:  # a reporting extra: never lose the line for it
+        log("step model skipped: %r" % (e,))
+        model = None
+    if model is not None and head["ms_per_step"] > 0:
+        roof["step_model_flops"] = model
+        roof["step_frac_fp64_peak"] = model / (head["ms_per_step"] / 1e3) / (PEAK["fp64"][0] * 1e12)
     dtype = {"fp64": "f64", "c64": "c64+f64", "bf16x3": "bf16x3+f64"}[args.precision]
     out = {
         "metric": METRIC, "value": head["steps_per_s"], "unit": "steps/s", "n_gpus": 1,

@@ -145,3 +145,18 @@ def test_eigh_top_rejects_bad_arguments():
         with pytest.raises(mpsim.MpsError) as e:
             mpsim.eigh_top(G, q, eig_path=path)
         assert e.value.status == mpsim.MPS_E_INVAL
+
+
+def test_step_flop_model():
+    """The whole-step work model of bench.py (standard two-site updates at
+    saturated bonds, from the planner's own schedule): the largest term is
+    the Gram matrix and reduction of the 16384-wide updates, so halving chi
+    at 6x8 divides the model by about 8; the gate-by-gate schedule has no
+    model. Block-pair schedule at 6x8, chi = 1024: 1.37e15 flops."""
+    import bench
+    f = {chi: bench.step_model_flops(6, 8, chi, 1) for chi in (512, 1024)}
+    assert abs(f[1024] / 1.367e15 - 1) < 0.01
+    assert 6.0 < f[1024] / f[512] < 10.0
+    f2 = bench.step_model_flops(6, 8, 1024, 2)
+    assert 0.5 * f[1024] < f2 < f[1024]        # rotating rows: fewer, narrower updates
+    assert bench.step_model_flops(6, 8, 1024, 4) is None
