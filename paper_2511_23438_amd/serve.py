@@ -17,6 +17,10 @@ sharing the GPU with the other instances); queue wait (arrival to
 admission) is reported separately. With an admission window, requests not
 admitted by its end are left unserved; with a hard stop, workers stop
 after their current step, and steps completed until then still count.
+A request the library rejects (an invalid configuration, or a footprint
+above the whole budget) is counted as rejected; one whose instance cannot
+be created (device allocation failed) is reported with its error, and the
+others are served.
 """
 from __future__ import annotations
 
@@ -108,8 +112,12 @@ class Server:
         `hard_stop_s`: stop every instance after its current step."""
         t0 = time.perf_counter()
         pending = sorted(enumerate(trace), key=lambda x: x[1].arrival_s)
-        need = {rid: mpsim.footprint_bytes(mpsim.config_from_instance(req.inst))
-                for rid, req in pending}
+        need = {}
+        for rid, req in pending:
+            try:
+                need[rid] = mpsim.footprint_bytes(mpsim.config_from_instance(req.inst))
+            except mpsim.MpsError:
+                need[rid] = None             # invalid configuration: rejected on arrival
         queue: list[tuple[int, Request]] = []
         active: dict[int, Active] = {}
         results: list[Result] = []
@@ -139,11 +147,16 @@ class Server:
             # admission by footprint, every round
             still = []
             for rid, req in queue:
-                if need[rid] > self.budget:
+                if need[rid] is None or need[rid] > self.budget:
                     rejected.append(rid)
                 elif (admitting and not stop.is_set() and len(active) < self.max_active
                       and used + need[rid] <= self.budget):
-                    a = self._admit(req, rid, now, need[rid])
+                    try:
+                        a = self._admit(req, rid, now, need[rid])
+                    except mpsim.MpsError as e:
+                        results.append(Result(rid, req.inst, None, now - req.arrival_s, [],
+                                              False, repr(e)))
+                        continue
                     a.thread = threading.Thread(target=self._worker, args=(a, stop, done),
                                                 daemon=True)
                     active[rid] = a

@@ -58,6 +58,19 @@ def test_served_hard_stop_counts_completed_steps():
     assert not out["errors"]
 
 
+def test_served_invalid_request_is_rejected_and_the_rest_served():
+    """A request with an invalid configuration (chi = 0) is rejected on
+    arrival; the requests around it are served and match their runs alone."""
+    trace = _small_trace(n=4, seed=13)
+    trace[1].inst.chi = 0
+    srv = serve.Server(1 << 40, max_active=4, seed=200)
+    out = srv.run(trace)
+    assert out["rejected"] == 1 and out["completed"] == 3 and not out["errors"]
+    for res in out["results"]:
+        alone = serve.run_alone(res.inst, seed=200 + res.rid)
+        assert res.obs["z"] == alone["z"]
+
+
 @pytest.mark.parametrize("chi_cap,precision", [(32, "fp64"), (256, "c64")])
 def test_batched_call_equals_sequential(chi_cap, precision):
     """The batched entry point on the batched workload set (grids 4x5..6x6,
