@@ -136,3 +136,32 @@ def test_rank_deficient_state_keeps_exact_zeros():
     assert np.max(np.abs(f_gpu - f_ora)) < TOL
     assert sim.bond_dims() == ora.bond_dims()
     sim.free()
+
+
+def test_batched_step_isolates_a_failing_instance():
+    """One instance of a batched call holds a NaN: its handle fails at the
+    next synchronising call, while the other instances of the same call keep
+    exactly the results they have alone."""
+    R, Cc, chi = 3, 4, 8
+    good = [workloads.random_mps(R, Cc, chi, 60 + k) for k in range(3)]
+    bad_sites, bad_centre = workloads.random_mps(R, Cc, chi, 64)
+    bad_sites[1] = bad_sites[1].copy()
+    bad_sites[1][0, 0, 0] = np.nan
+    sims = []
+    for sites, centre in good[:1] + [(bad_sites, bad_centre)] + good[1:]:
+        s = mpsim.Simulation(mpsim.make_config(R, Cc, chi))
+        s.set_state(sites, centre)
+        sims.append(s)
+    mpsim.apply_batched(sims, 2)
+    assert _status(sims[1].sync) == mpsim.MPS_E_NUMERIC
+    for k, s in enumerate([sims[0], sims[2], sims[3]]):
+        sites, centre = good[k]
+        ref = mpsim.Simulation(mpsim.make_config(R, Cc, chi))
+        ref.set_state(sites, centre)
+        ref.step(2)
+        a, b = s.measure(), ref.measure()
+        for key in ("z", "z2", "log_fidelity"):
+            assert a[key] == b[key]
+        ref.free()
+    for s in sims:
+        s.free()
