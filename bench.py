@@ -570,8 +570,9 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("this build runs on one GPU only: multi-GPU runs are not supported "
-              "(--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU: runs on several GPUs are not supported "
+              "(--gpus must be 1; independent instances shard by placing whole "
+              "instances on each GPU)", file=sys.stderr)
         return 2
     deadline = T_PROC0 + args.budget
 
